@@ -1,0 +1,431 @@
+"""Emit HIP device code and a JSON table description for each spline.
+
+For every reference sub-region the emitted code contains (Sec. 4.3, Sec. 4.4):
+
+  * ``<name>_eval_r<k>(c, y0, y1, y2)``: the sub-region polynomial in
+    multivariate Horner form.  The coefficients of the monomials are first
+    formed from the fetched stencil values (one group holding every tap), then
+    a single Horner pass runs over the local coordinates u = y - frame.
+  * ``<name>_eval_grad_r<k>``: value and the three partial derivatives in the
+    reference frame (derivatives of the sub-region polynomial, Sec. 3).
+  * ``<name>_weights_r<k>``: the per-tap weights w_j(u), each in Horner form
+    (group size one), used by the backward pass.
+
+For a tensor-product spline (exact factorisation checked here) the code is the
+separable contraction instead of the expanded polynomial.
+
+The JSON file records the stencils, frames and exact rational polynomials so a
+plain CPU interpreter can check the tables without a GPU.
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import os
+from fractions import Fraction
+from typing import Dict, List, Sequence, Tuple
+
+import numpy as np
+
+from .derive import BoxSpline, Derived, derive_region
+from .poly import Poly
+from .specs import SPECS, Spec, Region
+
+F = Fraction
+HERE = os.path.dirname(os.path.abspath(__file__))
+OUT_DIR = os.path.join(os.path.dirname(HERE), "csrc", "generated")
+
+
+def flit(x) -> str:
+    """FP32 literal (round-to-nearest of the exact rational)."""
+    v = float(np.float32(float(x)))
+    if v == 0:
+        return "0.0f"
+    r = repr(v)
+    if "e" not in r and "." not in r:
+        r += ".0"
+    return r + "f"
+
+
+# ----------------------------------------------------------- frame choice
+
+def _region_samples(region: Region, verts, n=4000, seed=7):
+    rng = np.random.default_rng(seed)
+    V = np.array([[float(x) for x in v] for v in verts])
+    w = rng.dirichlet(np.ones(len(V)), size=n)
+    return w @ V
+
+
+def condition(polys: Sequence[Poly], frame, pts) -> float:
+    """max over sample points of sum_j sum_m |W_jm| |u^m| (a-priori error scale)."""
+    U = pts - np.array([float(x) for x in frame])
+    tot = np.zeros(len(U))
+    for p in polys:
+        q = p.translate(frame)
+        for e, c in q.t.items():
+            tot += abs(float(c)) * np.abs(np.prod([U[:, i] ** e[i] for i in range(len(e))], axis=0))
+    return float(tot.max())
+
+
+def choose_frame(d: Derived, region: Region, max_cond=6.5):
+    pts = _region_samples(region, d.vertices)
+    cands = [tuple(F(0) for _ in d.frame), d.frame] + list(d.vertices)
+    best = None
+    for fr in cands:
+        loc = [p.translate(fr) for p in d.polys]
+        nnz = sum(len(p.t) for p in loc)
+        cond = condition(d.polys, fr, pts)
+        key = (cond > max_cond, nnz, cond)
+        if best is None or key < best[0]:
+            best = (key, fr, nnz, cond)
+    return best[1], best[2], best[3]
+
+
+# ----------------------------------------------------------- code helpers
+
+def horner(terms: Dict[Tuple[int, ...], str], nvars: int, names: Sequence[str]) -> str:
+    """Nested multivariate Horner expression for sum_e terms[e] * u^e."""
+    if not terms:
+        return "0.0f"
+
+    def rec(tms: Dict[Tuple[int, ...], str], var: int) -> str:
+        if var == nvars:
+            assert len(tms) == 1
+            return next(iter(tms.values()))
+        groups: Dict[int, Dict] = {}
+        for e, t in tms.items():
+            groups.setdefault(e[var], {})[e] = t
+        kmax = max(groups)
+        acc = rec(groups[kmax], var + 1)
+        for k in range(kmax - 1, -1, -1):
+            if k in groups:
+                acc = "fmaf(%s, %s, %s)" % (acc, names[var], rec(groups[k], var + 1))
+            else:
+                acc = "(%s) * %s" % (acc, names[var])
+        return acc
+
+    return rec(terms, 0)
+
+
+def lin_comb(pairs: List[Tuple[str, F]]) -> str:
+    """sum of var * const as a chain of fmaf."""
+    pairs = [(v, c) for v, c in pairs if c != 0]
+    if not pairs:
+        return "0.0f"
+    v0, c0 = pairs[0]
+    expr = "%s * %s" % (v0, flit(c0))
+    for v, c in pairs[1:]:
+        expr = "fmaf(%s, %s, %s)" % (v, flit(c), expr)
+    return expr
+
+
+# ----------------------------------------------------------- emission
+
+class SplineCode:
+    def __init__(self, spec: Spec):
+        self.spec = spec
+        self.bs = BoxSpline(spec.s, spec.Xi, spec.det_L)
+        self.regions: List[Derived] = [derive_region(spec, self.bs, r) for r in spec.regions]
+        self.frames, self.nnz, self.cond = [], [], []
+        for d, r in zip(self.regions, spec.regions):
+            fr, nnz, cond = choose_frame(d, r)
+            self.frames.append(fr)
+            self.nnz.append(nnz)
+            self.cond.append(cond)
+        # union stencil (order: first region's taps, then new ones)
+        union: List[Tuple[int, ...]] = []
+        for d in self.regions:
+            for o in d.taps:
+                if o not in union:
+                    union.append(o)
+        # order taps for locality: z-major, then y, then x (x fastest)
+        union.sort(key=lambda o: (o[2], o[1], o[0]))
+        self.union = union
+        self.tensor = self._tensor_factors() if spec.symmetry == "none" else None
+
+    # tensor-product detection: w_(i,j,k)(y) == b_i(y0) b_j(y1) b_k(y2)
+    def _tensor_factors(self):
+        spec = self.spec
+        if len(self.regions) != 1:
+            return None
+        d = self.regions[0]
+        axis_dirs = [tuple(x[i] for x in spec.Xi) for i in range(spec.s)]
+        mult = []
+        for i in range(spec.s):
+            cnt = sum(1 for x in spec.Xi if sum(abs(v) for v in x) == abs(x[i]) and x[i] != 0)
+            mult.append(cnt)
+        if sum(mult) != len(spec.Xi):
+            return None
+        # 1D pieces from the same derivation in one dimension
+        from .specs import Region as R
+        from . import derive as dv
+
+        class Spec1:
+            s = 1
+            D = (1,)
+            shifts = [(0,)]
+
+            def in_lattice(self, n):
+                return True
+
+        fac = []
+        for i in range(spec.s):
+            bs1 = dv.BoxSpline(1, [(1,)] * mult[i], 1)
+            reg = R("unit", [((1,), 0), ((-1,), 1)], (F(1, 3),))
+            d1 = dv.derive_region(Spec1(), bs1, reg)
+            fac.append(dict(zip([o[0] for o in d1.taps], d1.polys)))
+        for o, p in zip(d.taps, d.polys):
+            prod = Poly.const(spec.s, 1)
+            for i in range(spec.s):
+                q = fac[i][o[i]]
+                lifted = Poly(spec.s, {tuple(e[0] if a == i else 0 for a in range(spec.s)): c
+                                       for e, c in q.t.items()})
+                prod = prod * lifted
+            if prod != p:
+                return None
+        return fac
+
+    # -- JSON description
+    def tables(self) -> dict:
+        spec = self.spec
+        regs = []
+        for d, fr, nnz, cond in zip(self.regions, self.frames, self.nnz, self.cond):
+            loc = [p.translate(fr) for p in d.polys]
+            regs.append({
+                "name": d.name,
+                "taps": [list(o) for o in d.taps],
+                "union_index": [self.union.index(o) for o in d.taps],
+                "frame": [str(x) for x in fr],
+                "vertices": [[str(x) for x in v] for v in d.vertices],
+                "nnz": nnz,
+                "cond": cond,
+                "weights": [{",".join(map(str, e)): str(c) for e, c in q.t.items()} for q in loc],
+            })
+        return {
+            "name": spec.name, "s": spec.s, "L": [list(r) for r in spec.L],
+            "Xi": [list(x) for x in spec.Xi], "D": list(spec.D), "shifts": [list(x) for x in spec.shifts],
+            "roe": spec.roe, "symmetry": spec.symmetry,
+            "selector": None if spec.selector is None else [list(spec.selector[0]), spec.selector[1]],
+            "degree": self.bs.degree, "union": [list(o) for o in self.union],
+            "radius": max(abs(v) for o in self.union for v in o),
+            "tensor": self.tensor is not None,
+            "regions": regs,
+        }
+
+    # -- counts
+    def fma_counts(self) -> dict:
+        if self.tensor is not None:
+            n = [len(f) for f in self.tensor]
+            nt = int(np.prod(n))
+            w = sum(sum(len(p.t) for p in f.values()) for f in self.tensor)
+            contract = nt + n[1] * n[2] + n[2]
+            return {"eval": w + contract, "weights": w + nt}
+        out = {}
+        ev = 0
+        for d, fr in zip(self.regions, self.frames):
+            loc = [p.translate(fr) for p in d.polys]
+            mons = set()
+            for q in loc:
+                mons |= set(q.t)
+            ev += sum(len(q.t) for q in loc) + len(mons)
+        out["eval"] = ev
+        out["weights"] = sum(self.nnz)
+        return out
+
+    # -- code
+    def emit(self) -> str:
+        spec = self.spec
+        nm = spec.name
+        L = []
+        L.append("// Generated by paper_2102_08518_amd.gen.emit from the exact sub-region analysis")
+        L.append("// of the %s box spline.  Do not edit; regenerate with" % nm)
+        L.append("//   python -m paper_2102_08518_amd.gen")
+        L.append("#pragma once")
+        L.append("")
+        L.append("namespace lsp {")
+        L.append("namespace gen {")
+        L.append("")
+        L.append("struct %s_tables {" % nm)
+        L.append("  static constexpr int kTaps = %d;       // union stencil size" % len(self.union))
+        L.append("  static constexpr int kRegions = %d;    // reference sub-regions" % len(self.regions))
+        L.append("  static constexpr int kRadius = %d;     // max |offset component|" % max(abs(v) for o in self.union for v in o))
+        L.append("  static constexpr int kDegree = %d;" % self.bs.degree)
+        L.append("  static constexpr bool kTensor = %s;" % ("true" if self.tensor is not None else "false"))
+        fc = self.fma_counts()
+        L.append("  static constexpr int kFmaEval = %d;    // FMAs of the value polynomial(s)" % fc["eval"])
+        L.append("  static constexpr int kFmaWeights = %d; // FMAs of all per-tap weights" % fc["weights"])
+        offs = ", ".join("{%d, %d, %d}" % o for o in self.union)
+        L.append("  // reference-frame stencil offsets o_j (lattice vectors), x fastest")
+        L.append("  static constexpr signed char kOff[kTaps][3] = {%s};" % offs)
+        par = ", ".join(str((o[0] & 1) | ((o[1] & 1) << 1) | ((o[2] & 1) << 2)) for o in self.union)
+        L.append("  // parity pattern of each offset: bit0 x, bit1 y, bit2 z")
+        L.append("  static constexpr unsigned char kParity[kTaps] = {%s};" % par)
+        for k, d in enumerate(self.regions):
+            mask = sum(1 << self.union.index(o) for o in d.taps)
+            L.append("  static constexpr unsigned long long kRegionMask%d = 0x%xull;" % (k, mask))
+        L.append("};")
+        L.append("")
+        if self.tensor is not None:
+            L += self._emit_tensor()
+        else:
+            for k in range(len(self.regions)):
+                L += self._emit_region(k)
+        L.append("}  // namespace gen")
+        L.append("}  // namespace lsp")
+        L.append("")
+        return "\n".join(L)
+
+    def _emit_region(self, k: int) -> List[str]:
+        nm = self.spec.name
+        d = self.regions[k]
+        fr = self.frames[k]
+        loc = [p.translate(fr) for p in d.polys]
+        uidx = [self.union.index(o) for o in d.taps]
+        L = []
+        mons = sorted(set().union(*[set(q.t) for q in loc]), key=lambda e: (-sum(e), e))
+        midx = {e: i for i, e in enumerate(mons)}
+        frame_lines = ["  const float u%d = y%d - %s;" % (i, i, flit(fr[i])) if fr[i] != 0
+                       else "  const float u%d = y%d;" % (i, i) for i in range(3)]
+        # value (monomial coefficients first, then one Horner pass)
+        L.append("// sub-region %d (%s): %d taps, frame (%s), %d weight terms, cond %.2f"
+                 % (k, d.name, len(d.taps), ", ".join(str(x) for x in fr), self.nnz[k], self.cond[k]))
+        L.append("__device__ __forceinline__ void %s_coef_r%d(const float* __restrict__ c, float* __restrict__ A) {" % (nm, k))
+        for e in mons:
+            pairs = [("c[%d]" % uidx[j], q.t[e]) for j, q in enumerate(loc) if e in q.t]
+            L.append("  A[%d] = %s;" % (midx[e], lin_comb(pairs)))
+        L.append("}")
+        L.append("")
+        L.append("__device__ __forceinline__ float %s_eval_r%d(const float* __restrict__ c, float y0, float y1, float y2) {" % (nm, k))
+        L += frame_lines
+        L.append("  float A[%d];" % len(mons))
+        L.append("  %s_coef_r%d(c, A);" % (nm, k))
+        L.append("  return %s;" % horner({e: "A[%d]" % midx[e] for e in mons}, 3, ["u0", "u1", "u2"]))
+        L.append("}")
+        L.append("")
+        # value + gradient
+        L.append("__device__ __forceinline__ float %s_eval_grad_r%d(const float* __restrict__ c, float y0, float y1, float y2," % (nm, k))
+        L.append("                                                float& g0, float& g1, float& g2) {")
+        L += frame_lines
+        L.append("  float A[%d];" % len(mons))
+        L.append("  %s_coef_r%d(c, A);" % (nm, k))
+        for r in range(3):
+            dt = {}
+            for e in mons:
+                if e[r]:
+                    e2 = list(e)
+                    e2[r] -= 1
+                    term = "A[%d]" % midx[e] if e[r] == 1 else "(A[%d] * %d.0f)" % (midx[e], e[r])
+                    dt[tuple(e2)] = term
+            L.append("  g%d = %s;" % (r, horner(dt, 3, ["u0", "u1", "u2"])))
+        L.append("  return %s;" % horner({e: "A[%d]" % midx[e] for e in mons}, 3, ["u0", "u1", "u2"]))
+        L.append("}")
+        L.append("")
+        # per-tap weights (union-indexed; taps outside this sub-region get 0)
+        L.append("__device__ __forceinline__ void %s_weights_r%d(float y0, float y1, float y2, float* __restrict__ w) {" % (nm, k))
+        L += frame_lines
+        for j in range(len(self.union)):
+            if j not in uidx:
+                L.append("  w[%d] = 0.0f;" % j)
+        for j, q in enumerate(loc):
+            L.append("  w[%d] = %s;" % (uidx[j], horner({e: flit(c) for e, c in q.t.items()}, 3, ["u0", "u1", "u2"])))
+        L.append("}")
+        L.append("")
+        return L
+
+    def _emit_tensor(self) -> List[str]:
+        nm = self.spec.name
+        fac = self.tensor
+        L = []
+        taps1 = [sorted(f) for f in fac]
+        for i in range(3):
+            L.append("// axis %d: 1D weights at offsets %s on [0,1)" % (i, taps1[i]))
+            L.append("__device__ __forceinline__ void %s_w1d_%d(float t, float* w, float* dw) {" % (nm, i))
+            for a, o in enumerate(taps1[i]):
+                q = fac[i][o]
+                L.append("  w[%d] = %s;" % (a, horner({e: flit(c) for e, c in q.t.items()}, 1, ["t"])))
+                dq = q.deriv(0)
+                L.append("  if (dw) dw[%d] = %s;" % (a, horner({e: flit(c) for e, c in dq.t.items()}, 1, ["t"])))
+            L.append("}")
+            L.append("")
+        n0, n1, n2 = (len(t) for t in taps1)
+        idx = {o: j for j, o in enumerate(self.union)}
+
+        def cidx(a, b, cc):
+            return idx[(taps1[0][a], taps1[1][b], taps1[2][cc])]
+
+        # value
+        L.append("__device__ __forceinline__ float %s_eval_r0(const float* __restrict__ c, float y0, float y1, float y2) {" % nm)
+        L.append("  float wx[%d], wy[%d], wz[%d];" % (n0, n1, n2))
+        L.append("  %s_w1d_0(y0, wx, nullptr); %s_w1d_1(y1, wy, nullptr); %s_w1d_2(y2, wz, nullptr);" % (nm, nm, nm))
+        L.append("  float f = 0.0f;")
+        for cc in range(n2):
+            L.append("  {")
+            L.append("    float r = 0.0f;")
+            for b in range(n1):
+                terms = " ".join("")
+                e = "c[%d] * wx[0]" % cidx(0, b, cc)
+                for a in range(1, n0):
+                    e = "fmaf(c[%d], wx[%d], %s)" % (cidx(a, b, cc), a, e)
+                L.append("    r = fmaf(%s, wy[%d], r);" % (e, b))
+            L.append("    f = fmaf(r, wz[%d], f);" % cc)
+            L.append("  }")
+        L.append("  return f;")
+        L.append("}")
+        L.append("")
+        # value + gradient
+        L.append("__device__ __forceinline__ float %s_eval_grad_r0(const float* __restrict__ c, float y0, float y1, float y2," % nm)
+        L.append("                                                float& g0, float& g1, float& g2) {")
+        L.append("  float wx[%d], wy[%d], wz[%d], dx[%d], dy[%d], dz[%d];" % (n0, n1, n2, n0, n1, n2))
+        L.append("  %s_w1d_0(y0, wx, dx); %s_w1d_1(y1, wy, dy); %s_w1d_2(y2, wz, dz);" % (nm, nm, nm))
+        L.append("  float f = 0.0f; g0 = 0.0f; g1 = 0.0f; g2 = 0.0f;")
+        for cc in range(n2):
+            L.append("  {")
+            L.append("    float r = 0.0f, rx = 0.0f, ry = 0.0f;")
+            for b in range(n1):
+                e = "c[%d] * wx[0]" % cidx(0, b, cc)
+                ed = "c[%d] * dx[0]" % cidx(0, b, cc)
+                for a in range(1, n0):
+                    e = "fmaf(c[%d], wx[%d], %s)" % (cidx(a, b, cc), a, e)
+                    ed = "fmaf(c[%d], dx[%d], %s)" % (cidx(a, b, cc), a, ed)
+                L.append("    { const float s = %s, sd = %s;" % (e, ed))
+                L.append("      r = fmaf(s, wy[%d], r); ry = fmaf(s, dy[%d], ry); rx = fmaf(sd, wy[%d], rx); }" % (b, b, b))
+            L.append("    f = fmaf(r, wz[%d], f); g2 = fmaf(r, dz[%d], g2);" % (cc, cc))
+            L.append("    g1 = fmaf(ry, wz[%d], g1); g0 = fmaf(rx, wz[%d], g0);" % (cc, cc))
+            L.append("  }")
+        L.append("  return f;")
+        L.append("}")
+        L.append("")
+        # weights
+        L.append("__device__ __forceinline__ void %s_weights_r0(float y0, float y1, float y2, float* __restrict__ w) {" % nm)
+        L.append("  float wx[%d], wy[%d], wz[%d];" % (n0, n1, n2))
+        L.append("  %s_w1d_0(y0, wx, nullptr); %s_w1d_1(y1, wy, nullptr); %s_w1d_2(y2, wz, nullptr);" % (nm, nm, nm))
+        for cc in range(n2):
+            for b in range(n1):
+                L.append("  { const float t = wy[%d] * wz[%d];" % (b, cc))
+                for a in range(n0):
+                    L.append("    w[%d] = wx[%d] * t;" % (cidx(a, b, cc), a))
+                L.append("  }")
+        L.append("}")
+        L.append("")
+        return L
+
+
+def generate(names=None, out_dir=OUT_DIR, verbose=True):
+    os.makedirs(out_dir, exist_ok=True)
+    names = names or list(SPECS)
+    result = {}
+    for nm in names:
+        sc = SplineCode(SPECS[nm])
+        code = sc.emit()
+        tab = sc.tables()
+        tab["fma"] = sc.fma_counts()
+        with open(os.path.join(out_dir, "%s.h" % nm), "w") as fh:
+            fh.write(code)
+        with open(os.path.join(out_dir, "%s.json" % nm), "w") as fh:
+            json.dump(tab, fh, indent=1, sort_keys=True)
+        result[nm] = tab
+        if verbose:
+            print("%-9s taps %3d regions %d fma %s frames %s cond %s" % (
+                nm, len(sc.union), len(sc.regions), tab["fma"],
+                [[str(x) for x in f] for f in sc.frames], ["%.2f" % c for c in sc.cond]))
+    return result

@@ -1,0 +1,101 @@
+"""The splines the library generates code for, with their lattices, regions of
+evaluation and reference sub-regions.
+
+Each spec states (Sec. 4.1.2, Sec. 4.1.3, Fig. 1):
+  * the lattice L Z^3 as Cartesian cosets n = D * idx + shift_m (the memory
+    layout is one array per coset, Sec. 4.1);
+  * the direction matrix Xi of the box spline;
+  * the ROE: a floor parallelepiped or the Voronoi cell of the lattice;
+  * the symmetry used to reach the reference sub-regions: none, coordinate
+    sign flips, or signed permutations (y = sort_desc |x - k|);
+  * the reference sub-regions as half-space systems a . y + b >= 0, each with
+    an interior point.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from fractions import Fraction as F
+from typing import List, Sequence, Tuple
+
+
+@dataclass
+class Region:
+    name: str
+    halfspaces: List[Tuple[Tuple, object]]
+    interior: Tuple
+
+
+@dataclass
+class Spec:
+    name: str
+    s: int
+    L: Sequence[Sequence[int]]
+    Xi: Sequence[Tuple[int, ...]]
+    D: Tuple[int, ...]
+    shifts: List[Tuple[int, ...]]
+    roe: str                # "floor" or "voronoi"
+    symmetry: str           # "none", "signs", "signed_perm"
+    regions: List[Region] = field(default_factory=list)
+    # region selector for several reference sub-regions: (normal, threshold):
+    # region 0 if normal . y <= threshold, else region 1
+    selector: Tuple = None
+
+    def in_lattice(self, n) -> bool:
+        return any(all((n[i] - sh[i]) % self.D[i] == 0 for i in range(self.s)) for sh in self.shifts)
+
+    @property
+    def det_L(self) -> int:
+        L = self.L
+        if self.s == 2:
+            return abs(L[0][0] * L[1][1] - L[0][1] * L[1][0])
+        return abs(L[0][0] * (L[1][1] * L[2][2] - L[1][2] * L[2][1])
+                   - L[0][1] * (L[1][0] * L[2][2] - L[1][2] * L[2][0])
+                   + L[0][2] * (L[1][0] * L[2][1] - L[1][1] * L[2][0]))
+
+
+E = [(1, 0, 0), (0, 1, 0), (0, 0, 1)]
+DIAG = [(1, 1, 1), (1, -1, -1), (-1, 1, -1), (-1, -1, 1)]
+
+# Tensor-product cubic B-spline on Z^3 (Xi = [I I I I]); floor parallelepiped
+# ROE [0,1)^3 is a single sub-region with no symmetry needed.
+TRICUBIC = Spec(
+    name="tricubic", s=3, L=[[1, 0, 0], [0, 1, 0], [0, 0, 1]], Xi=E * 4,
+    D=(1, 1, 1), shifts=[(0, 0, 0)], roe="floor", symmetry="none",
+    regions=[Region("unit_cube",
+                    [((1, 0, 0), 0), ((0, 1, 0), 0), ((0, 0, 1), 0),
+                     ((-1, 0, 0), 1), ((0, -1, 0), 1), ((0, 0, -1), 1)],
+                    (F(1, 2), F(1, 3), F(1, 5)))])
+
+# BCC lattice L = [[-1,1,1],[1,-1,1],[1,1,-1]] = 2Z^3 u (2Z^3 + 1); the four
+# diagonals each twice.  Voronoi ROE (truncated octahedron |y_i| <= 1,
+# sum |y_i| <= 3/2); the spline is invariant under all signed permutations, so
+# y = sort_desc(|x - k|) lands in the wedge 0 <= y2 <= y1 <= y0, which no knot
+# plane (y_i +- y_j in 2Z) crosses: one reference sub-region.
+BCC8 = Spec(
+    name="bcc8", s=3, L=[[-1, 1, 1], [1, -1, 1], [1, 1, -1]], Xi=DIAG * 2,
+    D=(2, 2, 2), shifts=[(0, 0, 0), (1, 1, 1)], roe="voronoi", symmetry="signed_perm",
+    regions=[Region("wedge",
+                    [((1, -1, 0), 0), ((0, 1, -1), 0), ((0, 0, 1), 0),
+                     ((-1, 0, 0), 1), ((-1, -1, -1), F(3, 2))],
+                    (F(1, 2), F(3, 10), F(1, 10)))])
+
+# FCC lattice D3 = {n : sum n even}, L = [[0,1,1],[1,0,1],[1,1,0]], stored as
+# 4 cosets of 2Z^3.  Six directions (1,+-1,0), (1,0,+-1), (0,1,+-1).  Voronoi
+# ROE (rhombic dodecahedron |y_i| + |y_j| <= 1); sign flips take a point to the
+# positive octant, which the knot plane y0 + y1 + y2 = 1 cuts into two
+# reference sub-regions (inner tetrahedron and outer piece).
+FCC6 = Spec(
+    name="fcc6", s=3, L=[[0, 1, 1], [1, 0, 1], [1, 1, 0]],
+    Xi=[(1, 1, 0), (1, -1, 0), (1, 0, 1), (1, 0, -1), (0, 1, 1), (0, 1, -1)],
+    D=(2, 2, 2), shifts=[(0, 0, 0), (1, 1, 0), (1, 0, 1), (0, 1, 1)],
+    roe="voronoi", symmetry="signs",
+    regions=[Region("inner",
+                    [((1, 0, 0), 0), ((0, 1, 0), 0), ((0, 0, 1), 0), ((-1, -1, -1), 1)],
+                    (F(3, 10), F(1, 5), F(1, 10))),
+             Region("outer",
+                    [((1, 0, 0), 0), ((0, 1, 0), 0), ((0, 0, 1), 0), ((1, 1, 1), -1),
+                     ((-1, -1, 0), 1), ((-1, 0, -1), 1), ((0, -1, -1), 1)],
+                    (F(1, 2), F(7, 20), F(1, 4)))],
+    selector=((1, 1, 1), 1))
+
+SPECS = {sp.name: sp for sp in (TRICUBIC, BCC8, FCC6)}

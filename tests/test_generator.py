@@ -1,0 +1,99 @@
+"""The sub-region generator: structural counts, the paper's worked example
+reproduced exactly, and the emitted tables checked against the oracle through
+a CPU interpreter of the device algorithm."""
+import json
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2102_08518_amd.gen import interp
+from paper_2102_08518_amd.gen.derive import BoxSpline, derive_region
+from paper_2102_08518_amd.gen.emit import SplineCode
+from paper_2102_08518_amd.gen.specs import SPECS, Region, Spec
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+rng = np.random.default_rng(77)
+ORACLE_SPLINE = {"tricubic": oracle.TRICUBIC, "bcc8": oracle.BCC8, "fcc6": oracle.FCC6}
+
+
+def test_generator_reproduces_fig1_zp_polynomial_exactly():
+    """Fig. 1: one reference sub-region {x0 >= |x1|} of the ROE [-1/2,1/2]^2 with
+    seven taps; its polynomial equals the printed one coefficient by coefficient."""
+    zp = Spec(name="zp", s=2, L=[[1, 0], [0, 1]], Xi=[(1, 0), (0, 1), (1, 1), (1, -1)],
+              D=(1, 1), shifts=[(0, 0)], roe="voronoi", symmetry="rot90",
+              regions=[Region("sub1", [((1, -1), 0), ((1, 1), 0), ((-1, 0), Fraction(1, 2))],
+                              (Fraction(3, 10), Fraction(1, 20)))])
+    bs = BoxSpline(2, zp.Xi, 1)
+    d = derive_region(zp, bs, zp.regions[0])
+    with open(os.path.join(GOLDEN, "zp_fig1.json")) as fh:
+        g = json.load(fh)
+    assert len(d.taps) == 7
+    assert sorted(d.taps) == sorted(tuple(o) for o in g["offsets"])
+    for o, row in zip(g["offsets"], g["weights"]):
+        p = d.polys[d.taps.index(tuple(o))]
+        expect = {tuple(e): Fraction(c) for e, c in zip(g["monomials"], row) if Fraction(c) != 0}
+        assert p.t == expect, (o, p)
+
+
+@pytest.mark.parametrize("name,taps,regions", [("tricubic", 64, 1), ("bcc8", 32, 1), ("fcc6", 16, 2)])
+def test_stencil_sizes(name, taps, regions):
+    """Tricubic: 64 fetches (Sec. 5.1); the FCC cubic spline has two reference
+    sub-regions (Sec. 5.1); every stencil has vol(supp)/|det L| sites."""
+    tab = interp.load_tables(name)
+    assert len(tab["regions"]) == regions
+    for reg in tab["regions"]:
+        assert len(reg["taps"]) == taps
+
+
+@pytest.mark.parametrize("name", ["tricubic", "bcc8", "fcc6"])
+def test_weights_sum_to_one_exactly(name):
+    tab = interp.load_tables(name)
+    for reg in tab["regions"]:
+        tot = {}
+        for w in reg["weights"]:
+            for k, v in w.items():
+                tot[k] = tot.get(k, Fraction(0)) + Fraction(v)
+        tot = {k: v for k, v in tot.items() if v != 0}
+        assert tot == {"0,0,0": Fraction(1)}
+
+
+@pytest.mark.parametrize("name", ["tricubic", "bcc8", "fcc6"])
+def test_interpreter_matches_oracle(name):
+    sp = ORACLE_SPLINE[name]
+    tab = interp.load_tables(name)
+    E = 9
+    dims = (E, E, E)
+    coeffs = [rng.uniform(-1, 1, (E, E, E)) for _ in range(sp.n_cosets)]
+    hi = (E - 1) * sp.D[0]
+    x = rng.uniform(-1.5, hi + 1.5, (2500, 3))  # interior, boundary and outside
+    a = interp.evaluate(tab, dims, coeffs, x)
+    b = oracle.evaluate(sp, dims, coeffs, x)
+    np.testing.assert_allclose(a, b, rtol=0, atol=1e-13)
+
+
+def test_interpreter_on_region_boundaries():
+    """Points on the sub-region boundaries (ties of the location step)."""
+    sp = oracle.BCC8
+    tab = interp.load_tables("bcc8")
+    E = 8
+    coeffs = [rng.uniform(-1, 1, (E, E, E)) for _ in range(2)]
+    base = rng.uniform(5, 9, (300, 3))
+    base[:100, 1] = base[:100, 0]            # |d_x| == |d_y| ties
+    base[100:200] = np.round(base[100:200])  # lattice and half-lattice points
+    base[200:, 2] = np.round(base[200:, 2] * 2) / 2
+    a = interp.evaluate(tab, (E,) * 3, coeffs, base)
+    b = oracle.evaluate(sp, (E,) * 3, coeffs, base)
+    np.testing.assert_allclose(a, b, rtol=0, atol=1e-13)
+
+
+@pytest.mark.slow
+def test_committed_headers_are_current(tmp_path):
+    from paper_2102_08518_amd.gen.emit import OUT_DIR, generate
+    generate(out_dir=str(tmp_path), verbose=False)
+    for nm in SPECS:
+        for ext in (".h", ".json"):
+            with open(os.path.join(OUT_DIR, nm + ext)) as a, open(os.path.join(tmp_path, nm + ext)) as b:
+                assert a.read() == b.read(), nm + ext
