@@ -1,0 +1,178 @@
+"""Throughput of lattice-spline evaluation on one MI355X.
+
+Workload: BCC lattice 2 x 64^3 coefficients (a smooth field plus N(0,0.01)
+noise), the 8-direction box spline, 2^22 uniform random query points held in
+HBM.  One step = one forward pass over all points (locate + symmetry
+transform, stencil gather, Horner evaluation, store).  `value` is forward
+points/s with FP32 coefficients; the same line reports BF16-coefficient
+forward, forward+backward (dL/dc and dL/dx) when the workload allows, the
+error against the FP64 CPU checker, the roofline of the forward kernel and
+the checker's own throughput on the host cores.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "query points/s fwd and fwd+bwd, BCC 8-dir box spline, FP32 vs BF16 coeffs @ stated err"
+PEAK_FP32_VECTOR_TFLOPS = 157.3   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2 (packed) x 2.4 GHz
+PEAK_FP32_NONPACKED_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def time_fn(fn, steps, warmup, stream):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(steps):
+        fn()
+    end.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / steps  # ms per call
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cpu-sample", type=int, default=1 << 15)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the evaluation runs on a single device "
+              "(--gpus %d requested)." % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2102_08518_amd import api, inputs
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    w = inputs.workload2()
+    E, c, x = w["E"], w["coeffs"], w["points"]
+    n = x.shape[0]
+    log("workload 2: BCC 2x%d^3, %d points" % (E, n))
+    sp = api.Spline.bcc8()
+    fma = sp.info.fma_eval
+    xt = torch.tensor(x, device=dev)
+    ct = torch.tensor(c, dtype=torch.float32, device=dev)
+    out = torch.empty(n, dtype=torch.float32, device=dev)
+    res = {}
+    vols = {}
+    for storage in ("f32", "bf16"):
+        vol = api.Volume(sp, (E, E, E), storage)
+        vol.set(ct)
+        vols[storage] = vol
+        ms = time_fn(lambda: vol.eval(xt, out), args.steps, args.warmup, stream)
+        f = out.double().cpu().numpy()
+        res[storage] = dict(ms=ms, pts_per_s=n / (ms * 1e-3), f=f)
+        log("%s forward: %.4f ms/step, %.3e points/s" % (storage, ms, n / (ms * 1e-3)))
+
+    # forward + backward (dL/dc, dL/dx) for an MSE loss against the field
+    fb = None
+    try:
+        g = torch.empty(n, dtype=torch.float32, device=dev).uniform_(-1e-6, 1e-6)
+        vol = vols["f32"]
+        wsb = vol.workspace_bytes(n)
+        ws = torch.empty(wsb + 256, dtype=torch.uint8, device=dev)
+
+        def step_fb():
+            vol.eval(xt, out)
+            vol.backward(xt, g, want_dc=True, want_dx=True, workspace=ws)
+
+        ms_fb = time_fn(step_fb, max(args.steps // 5, 3), 2, stream)
+        fb = dict(ms=ms_fb, pts_per_s=n / (ms_fb * 1e-3))
+        log("fwd+bwd: %.4f ms/step" % ms_fb)
+    except Exception as e:  # the backward coefficient pass may be unavailable
+        log("fwd+bwd not measured: %s" % e)
+
+    # accuracy against the FP64 checker on a seeded sample
+    import oracle
+    rng = np.random.default_rng(12)
+    idx = rng.choice(n, 512, replace=False)
+    cmax = float(np.abs(c).max())
+    err = {}
+    for storage, tdt in (("f32", torch.float32), ("bf16", torch.bfloat16)):
+        cs = torch.tensor(c, dtype=torch.float32).to(tdt).double().numpy()
+        ref = oracle.evaluate(oracle.BCC8, (E, E, E), list(cs), x[idx].astype(np.float64))
+        ref64 = oracle.evaluate(oracle.BCC8, (E, E, E), list(c), x[idx].astype(np.float64))
+        f = res[storage]["f"][idx]
+        err[storage] = dict(max_rel_vs_stored=float(np.abs(f - ref).max() / cmax),
+                            max_rel_vs_fp64=float(np.abs(f - ref64).max() / cmax))
+
+    ms = res["f32"]["ms"]
+    t_k = ms * 1e-3
+    flops = 2.0 * fma * n
+    achieved = flops / t_k / 1e12
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
+            "traffic": None,
+            "kernel": "k_eval<bcc8,f32,f32,value>",
+            "algorithmic_flops_per_point": 2 * fma,
+            "frac_of_nonpacked_peak": round(achieved / PEAK_FP32_NONPACKED_TFLOPS, 4),
+            "hbm_compulsory_GBs": round(16.0 * n / t_k / 1e9, 1),
+            "hbm_compulsory_frac": round(16.0 * n / t_k / 1e9 / PEAK_HBM_GBS, 4)}
+
+    cpu = None
+    if not args.no_cpu:
+        m = args.cpu_sample
+        sub = x[:m].astype(np.float64)
+        t0 = time.time()
+        oracle.evaluate(oracle.BCC8, (E, E, E), list(c), sub)
+        dt = time.time() - t0
+        cpu = {"value": round(m / dt, 1), "unit": "points/s", "cores": oracle.num_threads(),
+               "kind": "oracle",
+               "sample": "first %d of the %d workload points, FP64 naive convolution sum" % (m, n)}
+        log("cpu oracle: %.1f points/s on %d threads (%.1f s)" % (m / dt, oracle.num_threads(), dt))
+
+    line = {
+        "metric": METRIC,
+        "value": round(res["f32"]["pts_per_s"], 1),
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "BCC 2x64^3 (L rows [-1,1,1],[1,-1,1],[1,1,-1]), 8-direction box "
+                               "spline, smooth field + N(0,0.01) coefficients, 2^22 uniform "
+                               "interior points, forward",
+                   "points": n, "coeffs": int(c.size), "storage": "f32"},
+        "bf16": {"value": round(res["bf16"]["pts_per_s"], 1), "ms_per_step": round(res["bf16"]["ms"], 5),
+                 "speedup_vs_f32": round(res["f32"]["ms"] / res["bf16"]["ms"], 3),
+                 "max_rel_err_vs_fp64": err["bf16"]["max_rel_vs_fp64"],
+                 "max_rel_err_vs_stored": err["bf16"]["max_rel_vs_stored"]},
+        "f32_err": err["f32"],
+        "fwd_bwd": None if fb is None else {"value": round(fb["pts_per_s"], 1),
+                                            "ms_per_step": round(fb["ms"], 5)},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,221 @@
+/*
+ * lsp.h -- C ABI of the lattice-spline evaluation library (gfx950).
+ *
+ * The library evaluates the lattice convolution sum
+ *
+ *     f(x) = sum over lattice sites n in L Z^s of  c_n * phi(x - n)
+ *
+ * (Sec. 1, Eq. 1) at many query points, in the unrolled sub-region form of
+ * Sec. 4 (Algorithm 1): locate the region of evaluation and the sub-region,
+ * apply the symmetry transform to the reference sub-region, fetch the stencil
+ * coefficients and evaluate the reference polynomial in Horner form.
+ *
+ * Conventions shared by every entry point:
+ *   * Everything is extern "C"; no C++ exception crosses the boundary.
+ *   * Argument errors are detected on the host, synchronously, before any
+ *     work is queued; the call then returns a status other than LSP_OK and
+ *     `lsp_last_error()` (thread-local) holds a human-readable detail.
+ *   * Device work is queued asynchronously on the caller's `stream` (0 means
+ *     the null stream); a launch failure returns LSP_E_HIP.
+ *   * Pointers documented as "device" must be device-accessible memory of the
+ *     current HIP device; "host" pointers are read before the call returns.
+ *   * The caller owns every buffer it passes in; the library never frees
+ *     them.  The library owns its handles and the internal coefficient
+ *     buffer of a volume; each is released by the matching *_destroy call.
+ *   * lsp_eval, lsp_eval_grad and lsp_backward allocate nothing: scratch
+ *     space of the backward pass is a caller-provided workspace.
+ *   * Handles are immutable between lsp_volume_set_coeffs calls, so several
+ *     threads or streams may evaluate one volume concurrently.
+ *
+ * Coefficient layout (the memory lookup of Sec. 4.1: one array per Cartesian
+ * coset of the lattice).  A lattice L Z^3 is stored as n_cosets Cartesian
+ * cosets; coset m holds the sites n = D * (i, j, k) + shift_m with
+ * 0 <= i < dims[0], 0 <= j < dims[1], 0 <= k < dims[2], in C order [k][j][i]
+ * (i fastest).  Sites outside this range are taken as zero (zero padding).
+ *   Z^3  (L = I):                        1 coset,  D = 1
+ *   BCC  (L Z^3 = 2Z^3 u 2Z^3+(1,1,1)):  2 cosets, D = 2, shifts (0,0,0),(1,1,1)
+ *   FCC  (L Z^3 = {n : n_x+n_y+n_z even}): 4 cosets, D = 2,
+ *        shifts (0,0,0),(1,1,0),(1,0,1),(0,1,1)
+ *
+ * The basis function is phi(y) = |det L| * M_Xi(y + Xi*1/2): the box spline
+ * of the direction matrix Xi, centred, and scaled so that its lattice
+ * translates sum to one.
+ */
+#ifndef LSP_H
+#define LSP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum lsp_status {
+    LSP_OK = 0,
+    LSP_E_INVALID_ARG = 1,  /* null pointer, negative size, bad enum value */
+    LSP_E_UNSUPPORTED = 2,  /* (L, Xi) pair for which no code was generated */
+    LSP_E_DTYPE = 3,        /* dtype not accepted for this argument */
+    LSP_E_SHAPE = 4,        /* sizes out of the supported range */
+    LSP_E_WORKSPACE = 5,    /* workspace missing or smaller than required */
+    LSP_E_HIP = 6,          /* a HIP runtime call or kernel launch failed */
+    LSP_E_OOM = 7           /* device allocation failed */
+} lsp_status;
+
+typedef enum lsp_dtype {
+    LSP_F32 = 0,
+    LSP_F64 = 1,
+    LSP_BF16 = 2,
+    LSP_F16 = 3
+} lsp_dtype;
+
+typedef struct lsp_spline lsp_spline;  /* opaque: (L, Xi) and its generated code */
+typedef struct lsp_volume lsp_volume;  /* opaque: a spline plus bound coefficients */
+
+typedef struct lsp_spline_info {
+    int s;                 /* dimension (3) */
+    int kind;              /* 0 tricubic on Z^3, 1 BCC 8-direction, 2 FCC 6-direction */
+    int n_cosets;          /* Cartesian cosets of the lattice */
+    int D[3];              /* coset scale */
+    int shift[4][3];       /* coset shifts (first n_cosets rows used) */
+    int taps;              /* stencil size of one reference sub-region */
+    int union_taps;        /* union of the reference sub-regions' stencils */
+    int n_reference;       /* reference sub-regions (polynomials) */
+    int degree;            /* total degree of the reference polynomials */
+    int radius;            /* max |component| of a stencil offset, lattice units */
+    int fma_eval;          /* FMAs of the generated value code, per point */
+    int pad;               /* zero halo of the internal layout, coset units */
+} lsp_spline_info;
+
+/* Human-readable name of a status; never NULL. */
+const char* lsp_status_string(lsp_status st);
+
+/* Detail of the last error raised on the calling thread ("" if none). */
+const char* lsp_last_error(void);
+
+/* Library version string. */
+const char* lsp_version(void);
+
+/* --------------------------------------------------------------- splines */
+
+/*
+ * Create the spline of a lattice and a box-spline direction matrix
+ * (the pair (L, Xi) that Sec. 3 takes as the description of a shift-invariant
+ * space).
+ *   s       dimension; only 3 is supported.
+ *   L       host, s*s int32, row-major; the COLUMNS are the lattice
+ *           generators.  Any basis of the same lattice is accepted.
+ *   Xi      host, s*n_dirs int32, row-major; the COLUMNS are the directions.
+ *           Direction order and signs do not matter (phi is centred).
+ *   out     receives a handle owned by the caller (lsp_spline_destroy).
+ * Supported pairs: Z^3 with Xi = [I I I I] (tricubic B-spline); the BCC
+ * lattice with its four diagonals each taken twice; the FCC lattice with the
+ * six directions (1,+-1,0), (1,0,+-1), (0,1,+-1).  Anything else returns
+ * LSP_E_UNSUPPORTED.  Host only; touches no device.
+ */
+lsp_status lsp_spline_create(int s, const int32_t* L, const int32_t* Xi, int n_dirs,
+                             lsp_spline** out);
+void lsp_spline_destroy(lsp_spline* sp);
+/* Fill `out` (host) with the spline's description.  Host only. */
+lsp_status lsp_spline_get_info(const lsp_spline* sp, lsp_spline_info* out);
+
+/* --------------------------------------------------------------- volumes */
+
+/*
+ * Create a volume: the spline plus an internal, zero-padded device buffer of
+ * n_cosets * dims[0]*dims[1]*dims[2] coefficients stored as `storage`
+ * (LSP_F32, LSP_BF16 or LSP_F16; FP32 evaluation in every case).  The buffer
+ * is allocated on the current device and zero-filled before return.
+ *   dims    host, 3 int64, per-coset extent (X, Y, Z), each in [1, 2^20], with
+ *           the padded internal buffer below 2^31 bytes (the halo is a few
+ *           sites per side; see lsp_spline_info.pad).
+ * The volume keeps a reference to nothing the caller owns; the spline handle
+ * may be destroyed afterwards.
+ */
+lsp_status lsp_volume_create(const lsp_spline* sp, const int64_t dims[3], lsp_dtype storage,
+                             lsp_volume** out);
+void lsp_volume_destroy(lsp_volume* vol);
+lsp_status lsp_volume_info(const lsp_volume* vol, lsp_spline_info* spline, int64_t dims[3],
+                           lsp_dtype* storage);
+
+/*
+ * Load coefficients.  coset_ptrs: host array of n_cosets DEVICE pointers, each
+ * to dims[2]*dims[1]*dims[0] values of dtype `src` (F32, F64, BF16 or F16) in
+ * C order [k][j][i].  They are converted (round to nearest even) to the
+ * storage dtype and packed into the volume's internal layout on `stream`.
+ * The source buffers must stay valid until that work has run.
+ */
+lsp_status lsp_volume_set_coeffs(lsp_volume* vol, const void* const* coset_ptrs, lsp_dtype src,
+                                 hipStream_t stream);
+
+/* ------------------------------------------------------------ evaluation */
+
+/*
+ * Forward pass: out[i] = f(x_i) (Eq. 1, evaluated as in Algorithm 1).
+ *   pts        device, N*3 values of pts_dtype (F32 or F64), xyz interleaved.
+ *              With F64 points the lattice-relative offset x - k is formed in
+ *              FP64 and then rounded to FP32.
+ *   N          number of points, 0 <= N < 2^31 (N == 0 queues nothing).
+ *   out        device, N floats.
+ * A point with a NaN coordinate gives NaN; points outside the stored lattice
+ * see zero coefficients (infinite coordinates give 0).  Never faults on any
+ * coordinate value.
+ */
+lsp_status lsp_eval(const lsp_volume* vol, const void* pts, lsp_dtype pts_dtype, int64_t N,
+                    float* out, hipStream_t stream);
+
+/*
+ * Value and gradient: val[i] = f(x_i) (val may be NULL), grad[3i+a] = df/dx_a
+ * (x_i).  The gradient is the derivative of the sub-region polynomial carried
+ * back through the symmetry transform (Sec. 3: the symmetry analysis applies
+ * to the derivative polynomials as well).
+ */
+lsp_status lsp_eval_grad(const lsp_volume* vol, const void* pts, lsp_dtype pts_dtype, int64_t N,
+                         float* val, float* grad, hipStream_t stream);
+
+/*
+ * Bytes of device workspace lsp_backward needs for N points.
+ */
+lsp_status lsp_backward_workspace_size(const lsp_volume* vol, int64_t N, size_t* bytes);
+
+/*
+ * Backward pass of out = f(pts) for a loss with dL/df = dL_df (device, N floats):
+ *   dL_dc  (nullable) device, n_cosets * dims product floats in the same
+ *          coset-major C-order layout as lsp_volume_set_coeffs' sources:
+ *          dL/dc_n = sum_i dL_df[i] * phi(x_i - n).  Overwritten.
+ *          Computed without floating-point atomics; bit-reproducible.
+ *   dL_dx  (nullable) device, N*3 floats: dL/dx_i = dL_df[i] * grad f(x_i).
+ *   workspace, ws_bytes: device scratch of at least
+ *          lsp_backward_workspace_size(vol, N) bytes (needed when dL_dc is
+ *          requested), aligned to 256 bytes.
+ */
+lsp_status lsp_backward(const lsp_volume* vol, const void* pts, lsp_dtype pts_dtype, int64_t N,
+                        const float* dL_df, float* dL_dc, float* dL_dx, void* workspace,
+                        size_t ws_bytes, hipStream_t stream);
+
+/* ----------------------------------------------------------- diagnostics */
+
+/*
+ * Host-only diagnostics of the location step (no device work, no allocation)
+ * for a volume of this spline, dims and storage dtype.  For each of N points
+ * (host, N*3 doubles, rounded to FP32 as lsp_eval does with F32 points) it
+ * writes the byte offset of every union-stencil tap into the internal buffer
+ * (offs, host, N*union_taps int32) and a flag word (flags, host, N int32:
+ * bit0 active, bit1 NaN, bits 2.. reference sub-region).  Used to check on
+ * the CPU that every fetch of an active point stays inside the buffer.
+ */
+lsp_status lsp_debug_tap_offsets(const lsp_spline* sp, const int64_t dims[3], lsp_dtype storage,
+                                 const double* pts, int64_t N, int32_t* offs, int32_t* flags);
+/* Internal layout: out (host, 12 int32) = element, row, slice and coset
+ * strides in bytes, halo, kmin[3], kmax[3], storage code; *nbytes = buffer
+ * size in bytes. */
+lsp_status lsp_debug_geometry(const lsp_spline* sp, const int64_t dims[3], lsp_dtype storage,
+                              int32_t* out, size_t* nbytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LSP_H */

@@ -1,0 +1,224 @@
+"""Python binding of the lattice-spline library: torch tensors hold device
+memory and the current stream; every step of the computation runs in the HIP
+library (liblsp.so).  Names follow the C ABI in include/lsp.h.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _native as N
+
+_DT = {"f32": N.LSP_F32, "f64": N.LSP_F64, "bf16": N.LSP_BF16, "f16": N.LSP_F16}
+_TORCH_DT = {torch.float32: N.LSP_F32, torch.float64: N.LSP_F64, torch.bfloat16: N.LSP_BF16,
+             torch.float16: N.LSP_F16}
+
+# Direction matrices (columns are directions) and lattice generators
+# (columns are generators) of the supported splines.
+_E3 = np.eye(3, dtype=np.int32)
+_DIAG = np.array([(1, 1, 1), (1, -1, -1), (-1, 1, -1), (-1, -1, 1)], dtype=np.int32)
+_FCC_DIRS = np.array([(1, 1, 0), (1, -1, 0), (1, 0, 1), (1, 0, -1), (0, 1, 1), (0, 1, -1)],
+                     dtype=np.int32)
+LATTICES = {
+    "cc": _E3,
+    "bcc": np.array([[-1, 1, 1], [1, -1, 1], [1, 1, -1]], dtype=np.int32),
+    "fcc": np.array([[0, 1, 1], [1, 0, 1], [1, 1, 0]], dtype=np.int32),
+}
+DIRECTIONS = {
+    "tricubic": np.concatenate([_E3] * 4, axis=1),
+    "bcc8": np.concatenate([_DIAG.T, _DIAG.T], axis=1),
+    "fcc6": _FCC_DIRS.T.copy(),
+}
+
+
+def _stream(device: Optional[torch.device] = None) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr() if t is not None else None)
+
+
+class Spline:
+    """A (lattice, direction matrix) pair the library has generated code for."""
+
+    def __init__(self, L, Xi):
+        L = np.ascontiguousarray(np.asarray(L, dtype=np.int32))
+        Xi = np.ascontiguousarray(np.asarray(Xi, dtype=np.int32))
+        if L.shape != (3, 3) or Xi.ndim != 2 or Xi.shape[0] != 3:
+            raise ValueError("L must be 3x3 and Xi 3xn")
+        h = ctypes.c_void_p()
+        N.check(N.lib().lsp_spline_create(3, L.ctypes.data_as(N.i32p), Xi.ctypes.data_as(N.i32p),
+                                          Xi.shape[1], ctypes.byref(h)))
+        self._h = h
+        info = N.SplineInfo()
+        N.check(N.lib().lsp_spline_get_info(h, ctypes.byref(info)))
+        self.info = info
+
+    @classmethod
+    def tricubic(cls):
+        return cls(LATTICES["cc"], DIRECTIONS["tricubic"])
+
+    @classmethod
+    def bcc8(cls):
+        return cls(LATTICES["bcc"], DIRECTIONS["bcc8"])
+
+    @classmethod
+    def fcc6(cls):
+        return cls(LATTICES["fcc"], DIRECTIONS["fcc6"])
+
+    @property
+    def n_cosets(self) -> int:
+        return self.info.n_cosets
+
+    # -- host diagnostics of the location step (no device work)
+    def debug_tap_offsets(self, dims, pts, storage: str = "f32"):
+        pts = np.ascontiguousarray(np.asarray(pts, dtype=np.float64).reshape(-1, 3))
+        n = pts.shape[0]
+        d = (ctypes.c_int64 * 3)(*[int(v) for v in dims])
+        offs = np.empty((n, self.info.union_taps), dtype=np.int32)
+        flags = np.empty(n, dtype=np.int32)
+        N.check(N.lib().lsp_debug_tap_offsets(self._h, d, _DT[storage],
+                                              pts.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                              n, offs.ctypes.data_as(N.i32p),
+                                              flags.ctypes.data_as(N.i32p)))
+        return offs, flags
+
+    def debug_geometry(self, dims, storage: str = "f32"):
+        d = (ctypes.c_int64 * 3)(*[int(v) for v in dims])
+        g = np.empty(12, dtype=np.int32)
+        nb = ctypes.c_size_t()
+        N.check(N.lib().lsp_debug_geometry(self._h, d, _DT[storage], g.ctypes.data_as(N.i32p),
+                                           ctypes.byref(nb)))
+        keys = ("sx", "sy", "sz", "scs", "pad", "kmin0", "kmin1", "kmin2", "kmax0", "kmax1",
+                "kmax2", "ctype")
+        out = dict(zip(keys, (int(v) for v in g)))
+        out["nbytes"] = nb.value
+        return out
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            N.lib().lsp_spline_destroy(h)
+            self._h = None
+
+
+class Volume:
+    """A spline with coefficients bound in the library's internal layout."""
+
+    def __init__(self, spline: Spline, dims: Sequence[int], storage: str = "f32"):
+        self.spline = spline
+        self.dims = tuple(int(d) for d in dims)
+        self.storage = storage
+        d = (ctypes.c_int64 * 3)(*self.dims)
+        h = ctypes.c_void_p()
+        N.check(N.lib().lsp_volume_create(spline._h, d, _DT[storage], ctypes.byref(h)))
+        self._h = h
+        self.n_cosets = spline.n_cosets
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            N.lib().lsp_volume_destroy(h)
+            self._h = None
+
+    @property
+    def n_coeffs(self) -> int:
+        return self.n_cosets * self.dims[0] * self.dims[1] * self.dims[2]
+
+    def set(self, cosets) -> None:
+        """cosets: a (n_cosets, Z, Y, X) tensor or a list of (Z, Y, X) tensors
+        on the device; converted to the storage dtype in the library."""
+        if isinstance(cosets, torch.Tensor):
+            cosets = list(cosets.reshape(self.n_cosets, *self.dims[::-1]))
+        if len(cosets) != self.n_cosets:
+            raise ValueError("need %d coset arrays" % self.n_cosets)
+        cosets = [c.contiguous() for c in cosets]
+        for c in cosets:
+            if c.shape != self.dims[::-1] or not c.is_cuda:
+                raise ValueError("each coset must be a device tensor of shape %s" % (self.dims[::-1],))
+        dt = {c.dtype for c in cosets}
+        if len(dt) != 1:
+            raise ValueError("coset arrays must share a dtype")
+        arr = (ctypes.c_void_p * self.n_cosets)(*[c.data_ptr() for c in cosets])
+        N.check(N.lib().lsp_volume_set_coeffs(self._h, arr, _TORCH_DT[cosets[0].dtype],
+                                              _stream(cosets[0].device)))
+        self._keep = cosets  # keep the sources alive until the stream has consumed them
+
+    @staticmethod
+    def _pts(pts: torch.Tensor) -> torch.Tensor:
+        if pts.dim() != 2 or pts.shape[1] != 3:
+            raise ValueError("points must be (N, 3)")
+        if pts.dtype not in (torch.float32, torch.float64):
+            raise ValueError("points must be float32 or float64")
+        if not pts.is_cuda:
+            raise ValueError("points must be on the device")
+        return pts.contiguous()
+
+    def eval(self, pts: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        pts = self._pts(pts)
+        if out is None:
+            out = torch.empty(pts.shape[0], dtype=torch.float32, device=pts.device)
+        N.check(N.lib().lsp_eval(self._h, _ptr(pts), _TORCH_DT[pts.dtype], pts.shape[0], _ptr(out),
+                                 _stream(pts.device)))
+        return out
+
+    def eval_grad(self, pts: torch.Tensor, want_value: bool = True):
+        pts = self._pts(pts)
+        n = pts.shape[0]
+        val = torch.empty(n, dtype=torch.float32, device=pts.device) if want_value else None
+        grad = torch.empty(n, 3, dtype=torch.float32, device=pts.device)
+        N.check(N.lib().lsp_eval_grad(self._h, _ptr(pts), _TORCH_DT[pts.dtype], n, _ptr(val),
+                                      _ptr(grad), _stream(pts.device)))
+        return val, grad
+
+    def workspace_bytes(self, n: int) -> int:
+        b = ctypes.c_size_t()
+        N.check(N.lib().lsp_backward_workspace_size(self._h, n, ctypes.byref(b)))
+        return b.value
+
+    def backward(self, pts: torch.Tensor, dL_df: torch.Tensor, want_dc: bool = True,
+                 want_dx: bool = True, workspace: Optional[torch.Tensor] = None):
+        """(dL/dc as (n_cosets, Z, Y, X) float32 or None, dL/dx as (N, 3) or None)."""
+        pts = self._pts(pts)
+        n = pts.shape[0]
+        g = dL_df.contiguous().to(torch.float32)
+        dc = (torch.empty((self.n_cosets,) + self.dims[::-1], dtype=torch.float32,
+                          device=pts.device) if want_dc else None)
+        dx = torch.empty(n, 3, dtype=torch.float32, device=pts.device) if want_dx else None
+        wsb = self.workspace_bytes(n) if want_dc else 0
+        if wsb and (workspace is None or workspace.numel() < wsb):
+            workspace = torch.empty(wsb + 256, dtype=torch.uint8, device=pts.device)
+        ws_ptr, ws_len = None, 0
+        if wsb:
+            base = workspace.data_ptr()
+            ws_ptr = (base + 255) // 256 * 256
+            ws_len = workspace.numel() - (ws_ptr - base)
+        N.check(N.lib().lsp_backward(self._h, _ptr(pts), _TORCH_DT[pts.dtype], n, _ptr(g), _ptr(dc),
+                                     _ptr(dx), ctypes.c_void_p(ws_ptr), ws_len, _stream(pts.device)))
+        return dc, dx
+
+class LatticeSplineFn(torch.autograd.Function):
+    """f = sum_n c_n phi(x - n) with gradients for the points and the
+    coefficients.  coeffs is the (n_cosets, Z, Y, X) float32 tensor whose
+    values are (re)loaded into `vol` on every forward."""
+
+    @staticmethod
+    def forward(ctx, pts: torch.Tensor, coeffs: torch.Tensor, vol: Volume):
+        vol.set(coeffs.detach())
+        ctx.vol = vol
+        ctx.save_for_backward(pts)
+        return vol.eval(pts.detach())
+
+    @staticmethod
+    def backward(ctx, g: torch.Tensor):
+        (pts,) = ctx.saved_tensors
+        want_dx = ctx.needs_input_grad[0]
+        want_dc = ctx.needs_input_grad[1]
+        dc, dx = ctx.vol.backward(pts.detach(), g, want_dc=want_dc, want_dx=want_dx)
+        if dx is not None:
+            dx = dx.to(pts.dtype)
+        return dx, dc, None

@@ -1,0 +1,538 @@
+// Host side of the C ABI declared in include/lsp.h: spline recognition,
+// argument validation, volume storage and kernel dispatch.
+#include <hip/hip_runtime.h>
+
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lsp.h"
+#include "lsp_launch.h"
+#include "lsp_backward.h"
+#include "generated/bcc8.h"
+#include "generated/fcc6.h"
+#include "generated/tricubic.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+lsp_status fail(lsp_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+lsp_status hip_fail(hipError_t e, const char* what) {
+    return fail(LSP_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// ----------------------------------------------------------- lattices
+
+typedef long long i64;
+
+i64 det3(const i64 m[3][3]) {
+    return m[0][0] * (m[1][1] * m[2][2] - m[1][2] * m[2][1]) -
+           m[0][1] * (m[1][0] * m[2][2] - m[1][2] * m[2][0]) +
+           m[0][2] * (m[1][0] * m[2][1] - m[1][1] * m[2][0]);
+}
+
+// adj(m) with m * adj(m) = det(m) I
+void adj3(const i64 m[3][3], i64 a[3][3]) {
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            const int r0 = (j + 1) % 3, r1 = (j + 2) % 3, c0 = (i + 1) % 3, c1 = (i + 2) % 3;
+            a[i][j] = m[r0][c0] * m[r1][c1] - m[r0][c1] * m[r1][c0];
+        }
+}
+
+// L Z^3 == R Z^3  iff  |det L| == |det R| and L^{-1} R is an integer matrix.
+bool same_lattice(const i64 L[3][3], const i64 R[3][3]) {
+    const i64 dl = det3(L), dr = det3(R);
+    if (dl == 0 || (dl < 0 ? -dl : dl) != (dr < 0 ? -dr : dr)) return false;
+    i64 a[3][3];
+    adj3(L, a);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            i64 v = 0;
+            for (int k = 0; k < 3; ++k) v += a[i][k] * R[k][j];
+            if (v % dl != 0) return false;
+        }
+    return true;
+}
+
+struct SplineDef {
+    int kind;
+    const char* name;
+    i64 L[3][3];                 // columns are generators
+    std::vector<std::vector<int>> dirs;  // canonical directions, with repeats
+    int n_cosets;
+    int D;
+    int shift[4][3];
+    int taps, union_taps, n_reference, degree, radius, fma_eval, pad;
+    int omin, omax;              // per-axis offset range in global axes (lattice units)
+};
+
+std::vector<int> canon_dir(std::vector<int> d) {
+    int sg = 0;
+    for (int v : d)
+        if (v) { sg = v > 0 ? 1 : -1; break; }
+    for (int& v : d) v *= sg;
+    return d;
+}
+
+template <class T>
+void fill_counts(SplineDef& s) {
+    s.union_taps = T::kTaps;
+    s.n_reference = T::kRegions;
+    s.degree = T::kDegree;
+    s.radius = T::kRadius;
+    s.fma_eval = T::kFmaEval;
+    int lo = 0, hi = 0;
+    for (int j = 0; j < T::kTaps; ++j)
+        for (int a = 0; a < 3; ++a) {
+            lo = std::min(lo, (int)T::kOff[j][a]);
+            hi = std::max(hi, (int)T::kOff[j][a]);
+        }
+    s.omin = lo;
+    s.omax = hi;
+}
+
+const std::vector<SplineDef>& defs() {
+    static std::vector<SplineDef> v;
+    if (!v.empty()) return v;
+    {
+        SplineDef s{};
+        s.kind = lsp::kTricubic;
+        s.name = "tricubic";
+        i64 L[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+        memcpy(s.L, L, sizeof(L));
+        for (int r = 0; r < 4; ++r)
+            for (int a = 0; a < 3; ++a) {
+                std::vector<int> d(3, 0);
+                d[a] = 1;
+                s.dirs.push_back(d);
+            }
+        s.n_cosets = 1;
+        s.D = 1;
+        s.taps = 64;
+        fill_counts<lsp::gen::tricubic_tables>(s);
+        s.pad = 4;
+        v.push_back(s);
+    }
+    {
+        SplineDef s{};
+        s.kind = lsp::kBcc8;
+        s.name = "bcc8";
+        // generators (-1,1,1), (1,-1,1), (1,1,-1) as columns
+        i64 L[3][3] = {{-1, 1, 1}, {1, -1, 1}, {1, 1, -1}};
+        memcpy(s.L, L, sizeof(L));
+        const int diag[4][3] = {{1, 1, 1}, {1, -1, -1}, {-1, 1, -1}, {-1, -1, 1}};
+        for (int r = 0; r < 2; ++r)
+            for (int i = 0; i < 4; ++i)
+                s.dirs.push_back(canon_dir({diag[i][0], diag[i][1], diag[i][2]}));
+        s.n_cosets = 2;
+        s.D = 2;
+        int sh[2][3] = {{0, 0, 0}, {1, 1, 1}};
+        memcpy(s.shift, sh, sizeof(sh));
+        s.taps = 32;
+        fill_counts<lsp::gen::bcc8_tables>(s);
+        s.omin = -s.radius;
+        s.omax = s.radius;
+        s.pad = 5;
+        v.push_back(s);
+    }
+    {
+        SplineDef s{};
+        s.kind = lsp::kFcc6;
+        s.name = "fcc6";
+        i64 L[3][3] = {{0, 1, 1}, {1, 0, 1}, {1, 1, 0}};
+        memcpy(s.L, L, sizeof(L));
+        const int dd[6][3] = {{1, 1, 0}, {1, -1, 0}, {1, 0, 1}, {1, 0, -1}, {0, 1, 1}, {0, 1, -1}};
+        for (int i = 0; i < 6; ++i) s.dirs.push_back(canon_dir({dd[i][0], dd[i][1], dd[i][2]}));
+        s.n_cosets = 4;
+        s.D = 2;
+        int sh[4][3] = {{0, 0, 0}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1}};
+        memcpy(s.shift, sh, sizeof(sh));
+        s.taps = 16;
+        fill_counts<lsp::gen::fcc6_tables>(s);
+        s.omin = -s.radius;
+        s.omax = s.radius;
+        s.pad = 3;
+        v.push_back(s);
+    }
+    return v;
+}
+
+int elem_size(int ctype) { return ctype == lsp::kCF32 ? 4 : 2; }
+
+int ctype_of(lsp_dtype storage) {
+    switch (storage) {
+        case LSP_F32: return lsp::kCF32;
+        case LSP_BF16: return lsp::kCBF16;
+        case LSP_F16: return lsp::kCF16;
+        default: return -1;
+    }
+}
+
+lsp_status fail(lsp_status st, const char* fmt, ...);
+
+// Internal layout of a volume: per-coset padded grids, strides in bytes, and
+// the range of ROE lattice points whose stencil reaches a stored site.
+lsp_status make_geom(const SplineDef& d, const int64_t dims[3], int ctype, lsp::VolGeom* out,
+                     size_t* nbytes) {
+    for (int a = 0; a < 3; ++a)
+        if (dims[a] < 1 || dims[a] > (1 << 20))
+            return fail(LSP_E_SHAPE, "dims[%d] = %lld out of [1, 2^20]", a, (long long)dims[a]);
+    const int es = elem_size(ctype);
+    const i64 px = dims[0] + 2 * d.pad, py = dims[1] + 2 * d.pad, pz = dims[2] + 2 * d.pad;
+    const i64 total = px * py * pz * d.n_cosets * es;
+    if (total >= ((i64)1 << 31))
+        return fail(LSP_E_SHAPE, "padded coefficient buffer of %lld bytes exceeds 2^31", (long long)total);
+    lsp::VolGeom g{};
+    g.sx = es;
+    g.sy = (int)(px * es);
+    g.sz = (int)(px * py * es);
+    g.scs = (int)(px * py * pz * es);
+    g.pad = d.pad;
+    for (int a = 0; a < 3; ++a) {
+        int shmax = 0;
+        for (int m = 0; m < d.n_cosets; ++m) shmax = std::max(shmax, d.shift[m][a]);
+        const i64 maxsite = (i64)d.D * (dims[a] - 1) + shmax;
+        // some tap k + o (o in [omin, omax]) lies in [0, maxsite]
+        g.kmin[a] = -d.omax;
+        g.kmax[a] = (int)(maxsite - d.omin);
+    }
+    *out = g;
+    *nbytes = (size_t)total;
+    return LSP_OK;
+}
+
+}  // namespace
+
+struct lsp_spline {
+    SplineDef def;
+};
+
+struct lsp_volume {
+    SplineDef def;
+    int64_t dims[3];
+    lsp_dtype storage;
+    int ctype;
+    void* buf;
+    size_t nbytes;
+    int device;
+    lsp::VolGeom geom;
+};
+
+extern "C" {
+
+const char* lsp_status_string(lsp_status st) {
+    switch (st) {
+        case LSP_OK: return "ok";
+        case LSP_E_INVALID_ARG: return "invalid argument";
+        case LSP_E_UNSUPPORTED: return "unsupported spline";
+        case LSP_E_DTYPE: return "unsupported dtype";
+        case LSP_E_SHAPE: return "size out of range";
+        case LSP_E_WORKSPACE: return "workspace too small";
+        case LSP_E_HIP: return "HIP error";
+        case LSP_E_OOM: return "out of device memory";
+    }
+    return "unknown status";
+}
+
+const char* lsp_last_error(void) { return g_err.c_str(); }
+
+const char* lsp_version(void) { return "lsp 0.1 (gfx950)"; }
+
+lsp_status lsp_spline_create(int s, const int32_t* L, const int32_t* Xi, int n_dirs,
+                             lsp_spline** out) {
+    if (!out) return fail(LSP_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!L || !Xi) return fail(LSP_E_INVALID_ARG, "L or Xi is NULL");
+    if (s != 3) return fail(LSP_E_UNSUPPORTED, "only s = 3 is supported (got %d)", s);
+    if (n_dirs < 3 || n_dirs > 64) return fail(LSP_E_INVALID_ARG, "n_dirs %d out of [3, 64]", n_dirs);
+    i64 Lm[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) Lm[i][j] = L[i * 3 + j];
+    if (det3(Lm) == 0) return fail(LSP_E_INVALID_ARG, "L is singular");
+    std::vector<std::vector<int>> dirs;
+    for (int j = 0; j < n_dirs; ++j) {
+        std::vector<int> d = {Xi[0 * n_dirs + j], Xi[1 * n_dirs + j], Xi[2 * n_dirs + j]};
+        if (d[0] == 0 && d[1] == 0 && d[2] == 0)
+            return fail(LSP_E_INVALID_ARG, "direction %d is zero", j);
+        dirs.push_back(canon_dir(d));
+    }
+    std::sort(dirs.begin(), dirs.end());
+    for (const SplineDef& d : defs()) {
+        std::vector<std::vector<int>> want = d.dirs;
+        std::sort(want.begin(), want.end());
+        if (want == dirs && same_lattice(Lm, d.L)) {
+            lsp_spline* sp = new (std::nothrow) lsp_spline;
+            if (!sp) return fail(LSP_E_OOM, "host allocation failed");
+            sp->def = d;
+            *out = sp;
+            return LSP_OK;
+        }
+    }
+    return fail(LSP_E_UNSUPPORTED,
+                "no generated code for this (L, Xi): supported are the tricubic B-spline on Z^3, "
+                "the BCC 8-direction and the FCC 6-direction box splines");
+}
+
+void lsp_spline_destroy(lsp_spline* sp) { delete sp; }
+
+static void fill_info(const SplineDef& d, lsp_spline_info* o) {
+    memset(o, 0, sizeof(*o));
+    o->s = 3;
+    o->kind = d.kind;
+    o->n_cosets = d.n_cosets;
+    for (int a = 0; a < 3; ++a) o->D[a] = d.D;
+    memcpy(o->shift, d.shift, sizeof(o->shift));
+    o->taps = d.taps;
+    o->union_taps = d.union_taps;
+    o->n_reference = d.n_reference;
+    o->degree = d.degree;
+    o->radius = d.radius;
+    o->fma_eval = d.fma_eval;
+    o->pad = d.pad;
+}
+
+lsp_status lsp_spline_get_info(const lsp_spline* sp, lsp_spline_info* out) {
+    if (!sp || !out) return fail(LSP_E_INVALID_ARG, "NULL argument");
+    fill_info(sp->def, out);
+    return LSP_OK;
+}
+
+lsp_status lsp_volume_create(const lsp_spline* sp, const int64_t dims[3], lsp_dtype storage,
+                             lsp_volume** out) {
+    if (!out) return fail(LSP_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!sp || !dims) return fail(LSP_E_INVALID_ARG, "NULL argument");
+    const int ctype = ctype_of(storage);
+    if (ctype < 0) return fail(LSP_E_DTYPE, "storage dtype must be F32, BF16 or F16");
+    const SplineDef& d = sp->def;
+    lsp::VolGeom g{};
+    size_t total = 0;
+    lsp_status st = make_geom(d, dims, ctype, &g, &total);
+    if (st) return st;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    void* buf = nullptr;
+    e = hipMalloc(&buf, (size_t)total);
+    if (e != hipSuccess) return fail(LSP_E_OOM, "hipMalloc(%lld): %s", (long long)total, hipGetErrorString(e));
+    e = hipMemset(buf, 0, (size_t)total);
+    if (e != hipSuccess) {
+        (void)hipFree(buf);
+        return hip_fail(e, "hipMemset");
+    }
+    lsp_volume* v = new (std::nothrow) lsp_volume;
+    if (!v) {
+        (void)hipFree(buf);
+        return fail(LSP_E_OOM, "host allocation failed");
+    }
+    v->def = d;
+    memcpy(v->dims, dims, sizeof(v->dims));
+    v->storage = storage;
+    v->ctype = ctype;
+    v->buf = buf;
+    v->nbytes = (size_t)total;
+    v->device = dev;
+    v->geom = g;
+    *out = v;
+    return LSP_OK;
+}
+
+void lsp_volume_destroy(lsp_volume* vol) {
+    if (!vol) return;
+    if (vol->buf) (void)hipFree(vol->buf);
+    delete vol;
+}
+
+lsp_status lsp_volume_info(const lsp_volume* vol, lsp_spline_info* spline, int64_t dims[3],
+                           lsp_dtype* storage) {
+    if (!vol) return fail(LSP_E_INVALID_ARG, "vol is NULL");
+    if (spline) fill_info(vol->def, spline);
+    if (dims) memcpy(dims, vol->dims, sizeof(vol->dims));
+    if (storage) *storage = vol->storage;
+    return LSP_OK;
+}
+
+lsp_status lsp_volume_set_coeffs(lsp_volume* vol, const void* const* coset_ptrs, lsp_dtype src,
+                                 hipStream_t stream) {
+    if (!vol || !coset_ptrs) return fail(LSP_E_INVALID_ARG, "NULL argument");
+    if (src != LSP_F32 && src != LSP_F64 && src != LSP_BF16 && src != LSP_F16)
+        return fail(LSP_E_DTYPE, "source dtype %d not supported", (int)src);
+    for (int m = 0; m < vol->def.n_cosets; ++m)
+        if (!coset_ptrs[m]) return fail(LSP_E_INVALID_ARG, "coset_ptrs[%d] is NULL", m);
+    for (int m = 0; m < vol->def.n_cosets; ++m) {
+        hipError_t e = lsp::launch_pack(coset_ptrs[m], (int)src, vol->ctype, vol->buf, vol->dims,
+                                        vol->geom, m, stream);
+        if (e != hipSuccess) return hip_fail(e, "pack kernel launch");
+    }
+    return LSP_OK;
+}
+
+static lsp_status check_eval_args(const lsp_volume* vol, const void* pts, lsp_dtype pd, int64_t N) {
+    if (!vol) return fail(LSP_E_INVALID_ARG, "vol is NULL");
+    if (N < 0 || N >= ((int64_t)1 << 31)) return fail(LSP_E_SHAPE, "N = %lld out of [0, 2^31)", (long long)N);
+    if (pd != LSP_F32 && pd != LSP_F64) return fail(LSP_E_DTYPE, "points must be F32 or F64");
+    if (N > 0 && !pts) return fail(LSP_E_INVALID_ARG, "pts is NULL");
+    return LSP_OK;
+}
+
+static lsp_status run_eval(const lsp_volume* vol, const void* pts, lsp_dtype pd, int64_t N,
+                           int mode, float* out, float* grad, const float* gin, hipStream_t stream) {
+    lsp::EvalArgs a{};
+    a.kind = vol->def.kind;
+    a.ctype = vol->ctype;
+    a.pts_f64 = pd == LSP_F64;
+    a.mode = mode;
+    a.predicated = false;
+    a.pts = pts;
+    a.N = (int)N;
+    a.coef = vol->buf;
+    a.nbytes = (unsigned)vol->nbytes;
+    a.g = vol->geom;
+    a.out = out;
+    a.grad = grad;
+    a.gin = gin;
+    a.stream = stream;
+    hipError_t e = hipSuccess;
+    switch (a.kind) {
+        case lsp::kTricubic: e = lsp::launch_eval_tricubic(a); break;
+        case lsp::kBcc8: e = lsp::launch_eval_bcc8(a); break;
+        case lsp::kFcc6: e = lsp::launch_eval_fcc6(a); break;
+        default: return fail(LSP_E_UNSUPPORTED, "kind %d", a.kind);
+    }
+    if (e != hipSuccess) return hip_fail(e, "evaluation kernel launch");
+    return LSP_OK;
+}
+
+lsp_status lsp_eval(const lsp_volume* vol, const void* pts, lsp_dtype pts_dtype, int64_t N,
+                    float* out, hipStream_t stream) {
+    lsp_status st = check_eval_args(vol, pts, pts_dtype, N);
+    if (st) return st;
+    if (N > 0 && !out) return fail(LSP_E_INVALID_ARG, "out is NULL");
+    return run_eval(vol, pts, pts_dtype, N, lsp::kValue, out, nullptr, nullptr, stream);
+}
+
+lsp_status lsp_eval_grad(const lsp_volume* vol, const void* pts, lsp_dtype pts_dtype, int64_t N,
+                         float* val, float* grad, hipStream_t stream) {
+    lsp_status st = check_eval_args(vol, pts, pts_dtype, N);
+    if (st) return st;
+    if (N > 0 && !grad) return fail(LSP_E_INVALID_ARG, "grad is NULL");
+    return run_eval(vol, pts, pts_dtype, N, lsp::kValueGrad, val, grad, nullptr, stream);
+}
+
+lsp_status lsp_backward_workspace_size(const lsp_volume* vol, int64_t N, size_t* bytes) {
+    if (!vol || !bytes) return fail(LSP_E_INVALID_ARG, "NULL argument");
+    if (N < 0 || N >= ((int64_t)1 << 31)) return fail(LSP_E_SHAPE, "N = %lld out of [0, 2^31)", (long long)N);
+    *bytes = lsp::backward_workspace_bytes(vol->def.kind, vol->def.n_cosets, vol->dims, vol->def.pad,
+                                           N);
+    return LSP_OK;
+}
+
+lsp_status lsp_backward(const lsp_volume* vol, const void* pts, lsp_dtype pts_dtype, int64_t N,
+                        const float* dL_df, float* dL_dc, float* dL_dx, void* workspace,
+                        size_t ws_bytes, hipStream_t stream) {
+    lsp_status st = check_eval_args(vol, pts, pts_dtype, N);
+    if (st) return st;
+    if (N > 0 && !dL_df && (dL_dc || dL_dx)) return fail(LSP_E_INVALID_ARG, "dL_df is NULL");
+    if (dL_dx && N > 0) {
+        st = run_eval(vol, pts, pts_dtype, N, lsp::kGradX, nullptr, dL_dx, dL_df, stream);
+        if (st) return st;
+    }
+    if (dL_dc) {
+        const size_t need = lsp::backward_workspace_bytes(vol->def.kind, vol->def.n_cosets, vol->dims,
+                                                          vol->def.pad, N);
+        if (need > 0 && (!workspace || ws_bytes < need))
+            return fail(LSP_E_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+        if (((uintptr_t)workspace & 255) != 0)
+            return fail(LSP_E_WORKSPACE, "workspace must be 256-byte aligned");
+        lsp::BackwardArgs b{};
+        b.kind = vol->def.kind;
+        b.ctype = vol->ctype;
+        b.pts_f64 = pts_dtype == LSP_F64;
+        b.pts = pts;
+        b.N = (int)N;
+        b.g = vol->geom;
+        b.n_cosets = vol->def.n_cosets;
+        for (int a = 0; a < 3; ++a) b.dims[a] = (int)vol->dims[a];
+        b.dL_df = dL_df;
+        b.dL_dc = dL_dc;
+        b.ws = workspace;
+        b.ws_bytes = ws_bytes;
+        b.stream = stream;
+        hipError_t e = lsp::launch_backward_coef(b);
+        if (e != hipSuccess) return hip_fail(e, "backward kernel launch");
+    }
+    return LSP_OK;
+}
+
+// ------------------------------------------------------------ diagnostics
+
+lsp_status lsp_debug_tap_offsets(const lsp_spline* sp, const int64_t dims[3], lsp_dtype storage,
+                                 const double* pts, int64_t N, int32_t* offs, int32_t* flags) {
+    if (!sp || !dims || (N > 0 && (!pts || !offs || !flags)))
+        return fail(LSP_E_INVALID_ARG, "NULL argument");
+    const int ctype = ctype_of(storage);
+    if (ctype < 0) return fail(LSP_E_DTYPE, "storage dtype must be F32, BF16 or F16");
+    lsp::VolGeom geom{};
+    size_t nbytes = 0;
+    lsp_status st = make_geom(sp->def, dims, ctype, &geom, &nbytes);
+    if (st) return st;
+    const int kind = sp->def.kind;
+    const int nt = sp->def.union_taps;
+    for (int64_t i = 0; i < N; ++i) {
+        float xf[3] = {(float)pts[3 * i], (float)pts[3 * i + 1], (float)pts[3 * i + 2]};
+        lsp::Loc L;
+        switch (kind) {
+            case lsp::kTricubic: lsp::locate<lsp::kTricubic>(xf, geom, L); break;
+            case lsp::kBcc8: lsp::locate<lsp::kBcc8>(xf, geom, L); break;
+            default: lsp::locate<lsp::kFcc6>(xf, geom, L); break;
+        }
+        flags[i] = (L.active ? 1 : 0) | (L.nan ? 2 : 0) | (L.region << 2);
+        for (int j = 0; j < nt; ++j) {
+            int32_t v;
+            if (kind == lsp::kTricubic) {
+                using T = lsp::gen::tricubic_tables;
+                v = lsp::tap_offset<lsp::kTricubic>(L, T::kOff[j][0], T::kOff[j][1], T::kOff[j][2], T::kParity[j]);
+            } else if (kind == lsp::kBcc8) {
+                using T = lsp::gen::bcc8_tables;
+                v = lsp::tap_offset<lsp::kBcc8>(L, T::kOff[j][0], T::kOff[j][1], T::kOff[j][2], T::kParity[j]);
+            } else {
+                using T = lsp::gen::fcc6_tables;
+                v = lsp::tap_offset<lsp::kFcc6>(L, T::kOff[j][0], T::kOff[j][1], T::kOff[j][2], T::kParity[j]);
+            }
+            offs[i * nt + j] = v;
+        }
+    }
+    return LSP_OK;
+}
+
+lsp_status lsp_debug_geometry(const lsp_spline* sp, const int64_t dims[3], lsp_dtype storage,
+                              int32_t* out, size_t* nbytes) {
+    if (!sp || !dims || !out || !nbytes) return fail(LSP_E_INVALID_ARG, "NULL argument");
+    const int ctype = ctype_of(storage);
+    if (ctype < 0) return fail(LSP_E_DTYPE, "storage dtype must be F32, BF16 or F16");
+    lsp::VolGeom g{};
+    lsp_status st = make_geom(sp->def, dims, ctype, &g, nbytes);
+    if (st) return st;
+    int v[12] = {g.sx, g.sy, g.sz, g.scs, g.pad, g.kmin[0], g.kmin[1], g.kmin[2],
+                 g.kmax[0], g.kmax[1], g.kmax[2], ctype};
+    memcpy(out, v, sizeof(v));
+    return LSP_OK;
+}
+
+}  // extern "C"

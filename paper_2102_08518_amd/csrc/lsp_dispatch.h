@@ -1,0 +1,55 @@
+// Instantiation and launch of k_eval for one spline kind over coefficient
+// type x point type x mode (x predication for the two-polynomial spline).
+#pragma once
+
+#include "lsp_kernels.h"
+#include "lsp_launch.h"
+
+namespace lsp {
+
+constexpr int kBlock = 256;
+
+template <int KIND, class CT, class PT, int MODE, bool PRED>
+hipError_t launch_one(const EvalArgs& a) {
+    const int blocks = (a.N + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL((k_eval<KIND, CT, PT, MODE, PRED>), dim3(blocks), dim3(kBlock), 0, a.stream,
+                       static_cast<const PT*>(a.pts), a.N, a.coef, a.nbytes, a.g, a.out, a.grad,
+                       a.gin);
+    return hipGetLastError();
+}
+
+template <int KIND, class CT, class PT, bool PRED>
+hipError_t launch_mode(const EvalArgs& a) {
+    switch (a.mode) {
+        case kValue: return launch_one<KIND, CT, PT, kValue, PRED>(a);
+        case kValueGrad: return launch_one<KIND, CT, PT, kValueGrad, PRED>(a);
+        case kGradX: return launch_one<KIND, CT, PT, kGradX, PRED>(a);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int KIND, class CT, bool PRED>
+hipError_t launch_pt(const EvalArgs& a) {
+    return a.pts_f64 ? launch_mode<KIND, CT, double, PRED>(a) : launch_mode<KIND, CT, float, PRED>(a);
+}
+
+template <int KIND, bool PRED>
+hipError_t launch_ct(const EvalArgs& a) {
+    switch (a.ctype) {
+        case kCF32: return launch_pt<KIND, float, PRED>(a);
+        case kCBF16: return launch_pt<KIND, bf16_t, PRED>(a);
+        case kCF16: return launch_pt<KIND, f16_t, PRED>(a);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int KIND>
+hipError_t launch_kind(const EvalArgs& a) {
+    if (a.N <= 0) return hipSuccess;
+    if constexpr (KIND == kFcc6) {
+        if (a.predicated) return launch_ct<KIND, true>(a);
+    }
+    return launch_ct<KIND, false>(a);
+}
+
+}  // namespace lsp

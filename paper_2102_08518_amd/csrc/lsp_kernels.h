@@ -1,0 +1,155 @@
+// Forward and value+gradient kernels: one thread per query point, the four
+// steps of Algorithm 1 -- locate and transform (lsp_locate.h), fetch the
+// stencil coefficients, evaluate the reference sub-region polynomial in
+// Horner form (generated code), write the result.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
+#include "lsp_launch.h"
+#include "lsp_locate.h"
+#include "generated/bcc8.h"
+#include "generated/fcc6.h"
+#include "generated/tricubic.h"
+
+namespace lsp {
+
+// Buffer resource over the internal coefficient buffer: raw loads whose byte
+// offset is outside [0, nbytes) return 0 instead of touching memory, which is
+// also exactly the zero padding of the convolution sum.
+#define LSP_RSRC_FLAGS 0x00020000
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, unsigned nbytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)nbytes,
+                                             LSP_RSRC_FLAGS);
+}
+
+struct bf16_t { unsigned short b; };
+struct f16_t { unsigned short b; };
+
+template <class CT> struct Coef;
+template <> struct Coef<float> {
+    static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, int off) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+    }
+};
+template <> struct Coef<bf16_t> {
+    static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, int off) {
+        const unsigned h = __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
+        return __builtin_bit_cast(float, h << 16);
+    }
+};
+template <> struct Coef<f16_t> {
+    static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, int off) {
+        const unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
+        return (float)__builtin_bit_cast(_Float16, h);
+    }
+};
+
+template <int KIND> struct Tables;
+template <> struct Tables<kTricubic> { using T = gen::tricubic_tables; };
+template <> struct Tables<kBcc8> { using T = gen::bcc8_tables; };
+template <> struct Tables<kFcc6> { using T = gen::fcc6_tables; };
+
+// Fetch every tap of the union stencil (Algorithm 1's memory lookups through
+// the permuted stencil pi').
+template <int KIND, class CT>
+__device__ __forceinline__ void gather(const Loc& L, __amdgpu_buffer_rsrc_t r, float* c) {
+    using T = typename Tables<KIND>::T;
+#pragma unroll
+    for (int j = 0; j < T::kTaps; ++j)
+        c[j] = Coef<CT>::ld(r, tap_offset<KIND>(L, T::kOff[j][0], T::kOff[j][1], T::kOff[j][2],
+                                                T::kParity[j]));
+}
+
+// Reference polynomial value (the unrolled reference sub-region loop,
+// Sec. 4.3; the FCC spline has two reference polynomials).
+template <int KIND, bool PREDICATED>
+__device__ __forceinline__ float poly_value(const float* c, const Loc& L) {
+    if (KIND == kTricubic) return gen::tricubic_eval_r0(c, L.y[0], L.y[1], L.y[2]);
+    if (KIND == kBcc8) return gen::bcc8_eval_r0(c, L.y[0], L.y[1], L.y[2]);
+    if (PREDICATED) {
+        const float v0 = gen::fcc6_eval_r0(c, L.y[0], L.y[1], L.y[2]);
+        const float v1 = gen::fcc6_eval_r1(c, L.y[0], L.y[1], L.y[2]);
+        return L.region ? v1 : v0;
+    }
+    if (L.region) return gen::fcc6_eval_r1(c, L.y[0], L.y[1], L.y[2]);
+    return gen::fcc6_eval_r0(c, L.y[0], L.y[1], L.y[2]);
+}
+
+// Value and gradient in the reference frame.
+template <int KIND, bool PREDICATED>
+__device__ __forceinline__ float poly_value_grad(const float* c, const Loc& L, float* g) {
+    if (KIND == kTricubic) return gen::tricubic_eval_grad_r0(c, L.y[0], L.y[1], L.y[2], g[0], g[1], g[2]);
+    if (KIND == kBcc8) return gen::bcc8_eval_grad_r0(c, L.y[0], L.y[1], L.y[2], g[0], g[1], g[2]);
+    if (PREDICATED) {
+        float a[3], b[3];
+        const float v0 = gen::fcc6_eval_grad_r0(c, L.y[0], L.y[1], L.y[2], a[0], a[1], a[2]);
+        const float v1 = gen::fcc6_eval_grad_r1(c, L.y[0], L.y[1], L.y[2], b[0], b[1], b[2]);
+        for (int r = 0; r < 3; ++r) g[r] = L.region ? b[r] : a[r];
+        return L.region ? v1 : v0;
+    }
+    if (L.region) return gen::fcc6_eval_grad_r1(c, L.y[0], L.y[1], L.y[2], g[0], g[1], g[2]);
+    return gen::fcc6_eval_grad_r0(c, L.y[0], L.y[1], L.y[2], g[0], g[1], g[2]);
+}
+
+// Gradient back to global axes: y = G (x - k) with G a signed permutation,
+// so df/dx = G^T df/dy, i.e. component axis[r] is sgn[r] * df/dy_r.
+__device__ __forceinline__ void grad_to_global(const Loc& L, const float* gr, float* gx) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float v = 0.0f;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) v = (L.axis[r] == a) ? L.sgn[r] * gr[r] : v;
+        gx[a] = v;
+    }
+}
+
+
+
+template <class PT>
+__device__ __forceinline__ void load_point(const PT* __restrict__ pts, int i, PT x[3]) {
+    x[0] = pts[3 * (size_t)i + 0];
+    x[1] = pts[3 * (size_t)i + 1];
+    x[2] = pts[3 * (size_t)i + 2];
+}
+
+// MODE kValue:     out[i] = f(x_i)
+// MODE kValueGrad: out[i] = f(x_i) (if out), grad[3i..] = grad f(x_i)
+// MODE kGradX:     grad[3i..] = gin[i] * grad f(x_i)        (dL/dx)
+template <int KIND, class CT, class PT, int MODE, bool PREDICATED>
+__global__ __launch_bounds__(256) void k_eval(const PT* __restrict__ pts, int N,
+                                              const void* __restrict__ coef, unsigned nbytes,
+                                              VolGeom g, float* __restrict__ out,
+                                              float* __restrict__ grad,
+                                              const float* __restrict__ gin) {
+    using T = typename Tables<KIND>::T;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    PT x[3];
+    load_point(pts, i, x);
+    Loc L;
+    locate<KIND>(x, g, L);
+    const __amdgpu_buffer_rsrc_t r = make_rsrc(coef, nbytes);
+    float c[T::kTaps];
+    gather<KIND, CT>(L, r, c);
+    const float qnan = __builtin_nanf("");
+    if (MODE == kValue) {
+        const float f = poly_value<KIND, PREDICATED>(c, L);
+        out[i] = L.active ? f : (L.nan ? qnan : 0.0f);
+    } else {
+        float gr[3], gx[3];
+        const float f = poly_value_grad<KIND, PREDICATED>(c, L, gr);
+        grad_to_global(L, gr, gx);
+        const float fill = L.nan ? qnan : 0.0f;
+        float scale = 1.0f;
+        if (MODE == kGradX) scale = gin[i];
+        if (MODE == kValueGrad && out) out[i] = L.active ? f : fill;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) grad[3 * (size_t)i + a] = L.active ? scale * gx[a] : fill;
+    }
+}
+
+}  // namespace lsp

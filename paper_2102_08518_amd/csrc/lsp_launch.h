@@ -1,0 +1,40 @@
+// Internal interface between the host library and the kernel translation
+// units (one per spline kind, so they compile in parallel).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include "lsp_locate.h"
+
+namespace lsp {
+
+enum CoefType : int { kCF32 = 0, kCBF16 = 1, kCF16 = 2 };
+enum Mode : int { kValue = 0, kValueGrad = 1, kGradX = 2 };
+
+struct EvalArgs {
+    int kind;           // Kind
+    int ctype;          // CoefType of the internal buffer
+    bool pts_f64;       // points in FP64
+    int mode;           // Mode
+    bool predicated;    // FCC6: evaluate both reference polynomials and select
+    const void* pts;
+    int N;
+    const void* coef;
+    unsigned nbytes;
+    VolGeom g;
+    float* out;
+    float* grad;
+    const float* gin;
+    hipStream_t stream;
+};
+
+hipError_t launch_eval_tricubic(const EvalArgs& a);
+hipError_t launch_eval_bcc8(const EvalArgs& a);
+hipError_t launch_eval_fcc6(const EvalArgs& a);
+
+// Convert one caller coset array (C order [z][y][x], dims X,Y,Z, dtype
+// src_dtype as lsp_dtype) into the internal padded buffer.
+hipError_t launch_pack(const void* src, int src_dtype, int ctype, void* dst, const int64_t dims[3],
+                       const VolGeom& g, int coset, hipStream_t stream);
+
+}  // namespace lsp

@@ -1,0 +1,248 @@
+// Point location, symmetry transform and stencil addressing (Sec. 4.1.2 to
+// Sec. 4.2, Algorithm 1): everything a query point needs before the
+// coefficient fetches.  Written as __host__ __device__ so the host library can
+// run the same arithmetic for its bounds diagnostics.
+//
+// Internal coefficient layout: n_cosets arrays, each the per-coset grid
+// [z][y][x] surrounded by a zero halo of `pad` sites on every side.  Byte
+// offset of site idx in coset m:
+//     m*scs + (idx_z + pad)*sz + (idx_y + pad)*sy + (idx_x + pad)*sx
+// where idx = floor((n - shift_m) / D).  For D = 2 lattices floor(n/2)
+// equals (n - shift_m)/2 for the coset the site belongs to, so the coset only
+// selects the array.
+#pragma once
+
+#include <stdint.h>
+
+#ifndef __HIP_DEVICE_COMPILE__
+#include <math.h>
+#endif
+
+#ifndef LSP_HD
+#define LSP_HD __host__ __device__ __forceinline__
+#endif
+
+namespace lsp {
+
+enum Kind : int { kTricubic = 0, kBcc8 = 1, kFcc6 = 2 };
+
+// Geometry of one volume as the kernels see it.  All strides are in bytes.
+struct VolGeom {
+    int sx, sy, sz, scs;    // element, row, slice and coset strides
+    int pad;                // halo in coset units
+    int kmin[3], kmax[3];   // ROE lattice points k with any stored tap
+};
+
+// Result of locating one point.
+struct Loc {
+    float y[3];        // coordinates in the reference sub-region frame
+    int base[4];       // byte offset of the stencil origin, per tap parity class
+    int S[3];          // signed byte stride of each reference axis
+    int axis[3];       // global axis of each reference axis
+    float sgn[3];      // sign of each reference axis (reflection)
+    int region;        // reference sub-region (polynomial) index
+    bool active;       // some stencil tap lies in the stored lattice
+    bool nan;          // a coordinate was NaN
+};
+
+// Coordinates are clamped to +-2^22 before rounding so the integer
+// conversions below stay defined; such points are outside any volume.
+#define LSP_XCLAMP 4194304.0
+
+template <class PT>
+LSP_HD PT clampc(PT v) {
+    return v < (PT)-LSP_XCLAMP ? (PT)-LSP_XCLAMP : (v > (PT)LSP_XCLAMP ? (PT)LSP_XCLAMP : v);
+}
+
+LSP_HD float fl_floor(float v) { return floorf(v); }
+LSP_HD double fl_floor(double v) { return floor(v); }
+LSP_HD float fl_rint(float v) { return rintf(v); }
+LSP_HD double fl_rint(double v) { return rint(v); }
+LSP_HD bool is_nan(float v) { return v != v; }
+LSP_HD bool is_nan(double v) { return v != v; }
+
+template <class PT>
+LSP_HD void finish_common(const PT x[3], const PT k[3], const VolGeom& g, Loc& L, int ki[3],
+                          float d[3]) {
+    L.nan = is_nan(x[0]) || is_nan(x[1]) || is_nan(x[2]);
+    bool act = !L.nan;
+    for (int a = 0; a < 3; ++a) {
+        ki[a] = (int)k[a];
+        act = act && ki[a] >= g.kmin[a] && ki[a] <= g.kmax[a];
+    }
+    L.active = act;
+    for (int a = 0; a < 3; ++a) {
+        // inactive points take the ROE of the origin (a site of every
+        // lattice here) so that every fetch stays inside the buffer
+        d[a] = act ? (float)(x[a] - k[a]) : 0.0f;
+        if (!act) ki[a] = 0;
+    }
+}
+
+// Tensor-product cubic on Z^3: parallelepiped ROE [0,1)^3 via floor, one
+// sub-region, no symmetry (Sec. 4.1.2, the floor form of rho).
+template <class PT>
+LSP_HD void locate_tricubic(const PT xin[3], const VolGeom& g, Loc& L) {
+    PT x[3], k[3];
+    for (int a = 0; a < 3; ++a) {
+        x[a] = is_nan(xin[a]) ? xin[a] : clampc(xin[a]);
+        k[a] = is_nan(x[a]) ? (PT)0 : fl_floor(x[a]);
+    }
+    int ki[3];
+    float d[3];
+    finish_common(x, k, g, L, ki, d);
+    const int st[3] = {g.sx, g.sy, g.sz};
+    int b = 0;
+    for (int a = 0; a < 3; ++a) {
+        b += (ki[a] + g.pad) * st[a];
+        L.y[a] = d[a];
+        L.S[a] = st[a];
+        L.axis[a] = a;
+        L.sgn[a] = 1.0f;
+    }
+    L.base[0] = L.base[1] = L.base[2] = L.base[3] = b;
+    L.region = 0;
+}
+
+// BCC lattice 2Z^3 u (2Z^3 + 1): Voronoi ROE (nearest lattice point: the
+// nearer of the nearest even and the nearest odd point), then the signed
+// permutation y = sort_desc(|x - k|) into the reference wedge
+// 0 <= y2 <= y1 <= y0 (Sec. 4.1.2, 4.1.3, Fig. 1's transform column).
+template <class PT>
+LSP_HD void locate_bcc(const PT xin[3], const VolGeom& g, Loc& L) {
+    PT x[3], ke[3], ko[3], k[3];
+    PT de = 0, dodd = 0;
+    for (int a = 0; a < 3; ++a) {
+        x[a] = is_nan(xin[a]) ? (PT)0 : clampc(xin[a]);
+        ke[a] = (PT)2 * fl_rint(x[a] * (PT)0.5);
+        ko[a] = (PT)2 * fl_rint((x[a] - (PT)1) * (PT)0.5) + (PT)1;
+        de += (x[a] - ke[a]) * (x[a] - ke[a]);
+        dodd += (x[a] - ko[a]) * (x[a] - ko[a]);
+    }
+    const bool odd = dodd < de;
+    for (int a = 0; a < 3; ++a) k[a] = odd ? ko[a] : ke[a];
+    PT xr[3] = {xin[0], xin[1], xin[2]};
+    for (int a = 0; a < 3; ++a) if (!is_nan(xr[a])) xr[a] = x[a];
+    int ki[3];
+    float d[3];
+    finish_common(xr, k, g, L, ki, d);
+    const int q = ki[0] & 1;
+    const int st[3] = {g.sx, g.sy, g.sz};
+    int be = q * g.scs, bo = (1 - q) * g.scs;
+    float m[3];
+    int S[3], ax[3];
+    float sg[3];
+    for (int a = 0; a < 3; ++a) {
+        const int K = ki[a] >> 1;   // floor(k/2)
+        const bool neg = d[a] < 0.0f;
+        be += (K + g.pad) * st[a];
+        bo += (K + g.pad + q - (neg ? 1 : 0)) * st[a];
+        m[a] = neg ? -d[a] : d[a];
+        S[a] = neg ? -st[a] : st[a];
+        sg[a] = neg ? -1.0f : 1.0f;
+        ax[a] = a;
+    }
+    // sorting network, descending by |d|, carrying the stride, axis, sign
+#define LSP_CSWAP(i, j)                                                           \
+    {                                                                             \
+        const bool sw = m[i] < m[j];                                              \
+        const float tm = sw ? m[j] : m[i], um = sw ? m[i] : m[j];                 \
+        const int tS = sw ? S[j] : S[i], uS = sw ? S[i] : S[j];                   \
+        const int ta = sw ? ax[j] : ax[i], ua = sw ? ax[i] : ax[j];               \
+        const float ts = sw ? sg[j] : sg[i], us = sw ? sg[i] : sg[j];             \
+        m[i] = tm; m[j] = um; S[i] = tS; S[j] = uS;                               \
+        ax[i] = ta; ax[j] = ua; sg[i] = ts; sg[j] = us;                           \
+    }
+    LSP_CSWAP(0, 1)
+    LSP_CSWAP(1, 2)
+    LSP_CSWAP(0, 1)
+#undef LSP_CSWAP
+    for (int r = 0; r < 3; ++r) {
+        L.y[r] = m[r];
+        L.S[r] = S[r];
+        L.axis[r] = ax[r];
+        L.sgn[r] = sg[r];
+    }
+    L.base[0] = be;   // taps with all-even offsets
+    L.base[1] = bo;   // taps with all-odd offsets
+    L.base[2] = L.base[3] = be;
+    L.region = 0;
+}
+
+// Coset index of an FCC parity pattern (bit0 x, bit1 y, bit2 z):
+// 000 -> 0, 110 -> 1, 101 -> 2, 011 -> 3 (the order of the coset shifts).
+LSP_HD int fcc_coset(int p) { return (14400 >> (2 * p)) & 3; }
+
+// Index of an FCC tap parity pattern among {000, 110, 101, 011}.
+LSP_HD constexpr int fcc_class(int p) { return p == 0 ? 0 : (p == 3 ? 1 : (p == 5 ? 2 : 3)); }
+
+// FCC lattice {n : sum n even}: Voronoi ROE by rounding every coordinate and,
+// when the sum is odd, re-rounding the coordinate with the largest residual
+// the other way (Conway and Sloane's decoder for D3); the reflections
+// y = |x - k| map into the positive octant, where the plane
+// y0 + y1 + y2 = 1 splits the two reference sub-regions.
+template <class PT>
+LSP_HD void locate_fcc(const PT xin[3], const VolGeom& g, Loc& L) {
+    PT x[3], k[3], res[3];
+    int par = 0;
+    for (int a = 0; a < 3; ++a) {
+        x[a] = is_nan(xin[a]) ? (PT)0 : clampc(xin[a]);
+        k[a] = fl_rint(x[a]);
+        res[a] = x[a] - k[a];
+        par += (int)k[a];
+    }
+    PT ar[3];
+    for (int a = 0; a < 3; ++a) ar[a] = res[a] < (PT)0 ? -res[a] : res[a];
+    const int j = (ar[0] >= ar[1]) ? ((ar[0] >= ar[2]) ? 0 : 2) : ((ar[1] >= ar[2]) ? 1 : 2);
+    if (par & 1) {
+        for (int a = 0; a < 3; ++a)
+            if (a == j) k[a] += res[a] >= (PT)0 ? (PT)1 : (PT)-1;
+    }
+    PT xr[3] = {xin[0], xin[1], xin[2]};
+    for (int a = 0; a < 3; ++a) if (!is_nan(xr[a])) xr[a] = x[a];
+    int ki[3];
+    float d[3];
+    finish_common(xr, k, g, L, ki, d);
+    const int q = (ki[0] & 1) | ((ki[1] & 1) << 1) | ((ki[2] & 1) << 2);
+    const int st[3] = {g.sx, g.sy, g.sz};
+    const int pats[4] = {0, 3, 5, 6};
+    int common = 0;
+    int adj[3];
+    for (int a = 0; a < 3; ++a) {
+        const bool neg = d[a] < 0.0f;
+        common += ((ki[a] >> 1) + g.pad) * st[a];
+        adj[a] = (((q >> a) & 1) - (neg ? 1 : 0)) * st[a];
+        L.y[a] = neg ? -d[a] : d[a];
+        L.S[a] = neg ? -st[a] : st[a];
+        L.sgn[a] = neg ? -1.0f : 1.0f;
+        L.axis[a] = a;
+    }
+    for (int c = 0; c < 4; ++c) {
+        const int t = pats[c];
+        int b = fcc_coset(q ^ t) * g.scs + common;
+        for (int a = 0; a < 3; ++a)
+            if ((t >> a) & 1) b += adj[a];
+        L.base[c] = b;
+    }
+    L.region = (L.y[0] + L.y[1] + L.y[2] > 1.0f) ? 1 : 0;
+}
+
+template <int KIND, class PT>
+LSP_HD void locate(const PT x[3], const VolGeom& g, Loc& L) {
+    if (KIND == kTricubic) locate_tricubic(x, g, L);
+    else if (KIND == kBcc8) locate_bcc(x, g, L);
+    else locate_fcc(x, g, L);
+}
+
+// Byte offset of the tap with reference-frame offset o (a lattice vector)
+// and parity pattern par: the stencil origin of its parity class plus
+// floor(o/D) steps along each signed, permuted reference axis.
+template <int KIND>
+LSP_HD int tap_offset(const Loc& L, int o0, int o1, int o2, int par) {
+    if (KIND == kTricubic)
+        return L.base[0] + o0 * L.S[0] + o1 * L.S[1] + o2 * L.S[2];
+    const int cls = (KIND == kBcc8) ? (par ? 1 : 0) : fcc_class(par);
+    return L.base[cls] + (o0 >> 1) * L.S[0] + (o1 >> 1) * L.S[1] + (o2 >> 1) * L.S[2];
+}
+
+}  // namespace lsp

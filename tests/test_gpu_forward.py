@@ -1,0 +1,169 @@
+"""GPU parity of the forward and value+gradient kernels against the FP64 CPU
+checker, element by element on the same seeded inputs.
+
+Tolerances (FP32 evaluation): |f_gpu - f_ref| <= 2e-6 max|c| for values,
+where f_ref is the checker run on the coefficients as stored (FP32, BF16 or
+FP16 rounded on the host); against the unrounded coefficients the stored
+form adds at most u_q max|c| (u_bf16 = 2^-9, u_fp16 = 2^-11), because the
+weights are non-negative and sum to one.  Gradients: 2e-5 max|c| (the
+derivative polynomials have coefficients up to a few times those of the
+values)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2102_08518_amd import api, inputs
+
+pytestmark = pytest.mark.gpu
+
+ORC = {"tricubic": oracle.TRICUBIC, "bcc8": oracle.BCC8, "fcc6": oracle.FCC6}
+TORCH_DT = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}
+U_Q = {"f32": 2.0 ** -24, "bf16": 2.0 ** -9, "f16": 2.0 ** -11}
+
+
+def _stored(c, storage):
+    """Coefficients as the volume stores them, back in FP64 (host rounding)."""
+    return torch.tensor(c, dtype=torch.float32).to(TORCH_DT[storage]).to(torch.float64).numpy()
+
+
+def _mk(name, E, c, storage, dev, src=torch.float32):
+    sp = getattr(api.Spline, name)()
+    vol = api.Volume(sp, (E, E, E), storage)
+    vol.set(torch.tensor(c, dtype=src, device=dev))
+    return vol
+
+
+def _points(name, E, n, rng, outside=True):
+    lat = inputs.LATTICE[name]
+    hi = lat["D"] * (E - 1) + 1
+    x = rng.uniform(-4, hi + 4, (n, 3)) if outside else rng.uniform(*inputs.interior(name, E), (n, 3))
+    return x.astype(np.float32)
+
+
+@pytest.mark.parametrize("name", ["tricubic", "bcc8", "fcc6"])
+@pytest.mark.parametrize("storage", ["f32", "bf16", "f16"])
+def test_forward_matches_oracle(device, name, storage):
+    print("case forward", name, storage, flush=True)
+    rng = np.random.default_rng(100 + len(name) + len(storage))
+    E = 11
+    nc = ORC[name].n_cosets
+    c = rng.uniform(-1, 1, (nc, E, E, E))
+    x = _points(name, E, 3001, rng)               # ragged: not a multiple of the block
+    vol = _mk(name, E, c, storage, device)
+    f = vol.eval(torch.tensor(x, device=device)).cpu().numpy().astype(np.float64)
+    cs = _stored(c, storage)
+    ref = oracle.evaluate(ORC[name], (E, E, E), list(cs), x.astype(np.float64))
+    err = np.abs(f - ref).max()
+    assert err <= 2e-6 * np.abs(cs).max(), err
+    if storage != "f32":
+        ref64 = oracle.evaluate(ORC[name], (E, E, E), list(c), x.astype(np.float64))
+        assert np.abs(f - ref64).max() <= U_Q[storage] * np.abs(c).max() + 2e-6
+
+
+@pytest.mark.parametrize("name", ["tricubic", "bcc8", "fcc6"])
+def test_f64_points_and_f64_source(device, name):
+    """FP64 points (x - k formed in FP64, then rounded) and an FP64 source
+    array converted to FP32 storage inside the library."""
+    print("case f64", name, flush=True)
+    rng = np.random.default_rng(7)
+    E = 9
+    nc = ORC[name].n_cosets
+    c = rng.uniform(-1, 1, (nc, E, E, E))
+    x = _points(name, E, 1500, rng).astype(np.float64) + rng.uniform(-0.5, 0.5, (1500, 3)) * 1e-3
+    vol = _mk(name, E, c, "f32", device, src=torch.float64)   # F64 source, converted in the library
+    f = vol.eval(torch.tensor(x, device=device)).cpu().numpy().astype(np.float64)
+    cs = _stored(c, "f32")
+    ref = oracle.evaluate(ORC[name], (E, E, E), list(cs), x)
+    assert np.abs(f - ref).max() <= 2e-6
+
+
+@pytest.mark.parametrize("name", ["tricubic", "bcc8", "fcc6"])
+def test_value_and_gradient_match_oracle(device, name):
+    print("case grad", name, flush=True)
+    rng = np.random.default_rng(21)
+    E = 10
+    nc = ORC[name].n_cosets
+    c = rng.uniform(-1, 1, (nc, E, E, E))
+    x = _points(name, E, 2049, rng)
+    vol = _mk(name, E, c, "f32", device)
+    xt = torch.tensor(x, device=device)
+    val, grad = vol.eval_grad(xt)
+    cs = _stored(c, "f32")
+    fref, gref = oracle.evaluate(ORC[name], (E, E, E), list(cs), x.astype(np.float64), grad=True)
+    assert np.abs(val.cpu().numpy() - fref).max() <= 2e-6
+    assert np.abs(grad.cpu().numpy() - gref).max() <= 2e-5
+    # dL/dx = dL/df * grad f through the backward entry point
+    g = torch.tensor(rng.normal(size=x.shape[0]), dtype=torch.float32, device=device)
+    _, dx = vol.backward(xt, g, want_dc=False, want_dx=True)
+    np.testing.assert_allclose(dx.cpu().numpy(), g.cpu().numpy()[:, None] * gref, rtol=0,
+                               atol=2e-5 * float(g.abs().max()))
+
+
+@pytest.mark.parametrize("name", ["tricubic", "bcc8", "fcc6"])
+def test_edge_inputs(device, name):
+    """Empty input, NaN (-> NaN), infinities and far points (-> 0), exact
+    lattice sites and sub-region boundaries."""
+    print("case edges", name, flush=True)
+    E = 6
+    nc = ORC[name].n_cosets
+    rng = np.random.default_rng(5)
+    c = rng.uniform(-1, 1, (nc, E, E, E))
+    vol = _mk(name, E, c, "f32", device)
+    empty = vol.eval(torch.empty(0, 3, device=device))
+    assert empty.shape == (0,)
+    special = np.array([[np.nan, 1, 1], [1, np.nan, 1], [np.inf, 2, 2], [-np.inf, 2, 2],
+                        [1e30, 1, 1], [-1e30, 1, 1], [3e9, 3e9, 3e9], [-50, 2, 2], [2, 2, 200]],
+                       dtype=np.float32)
+    f = vol.eval(torch.tensor(special, device=device)).cpu().numpy()
+    assert np.isnan(f[0]) and np.isnan(f[1])
+    assert np.all(f[2:] == 0.0)
+    _, g = vol.eval_grad(torch.tensor(special, device=device))
+    g = g.cpu().numpy()
+    assert np.isnan(g[0]).all() and np.all(g[2:] == 0.0)
+    D = inputs.LATTICE[name]["D"]
+    hi = D * (E - 1)
+    sites = np.array([[a, b, cc] for a in range(0, hi + 1) for b in range(0, hi + 1)
+                      for cc in range(0, hi + 1)], dtype=np.float32)
+    ties = rng.uniform(1, hi, (600, 3)).astype(np.float32)
+    ties[:200, 1] = ties[:200, 0]
+    ties[200:400] = np.round(ties[200:400] * 2) / 2
+    ties[400:, 2] = ties[400:, 0] - ties[400:, 1] + 1.0
+    x = np.concatenate([sites, ties])
+    f = vol.eval(torch.tensor(x, device=device)).cpu().numpy()
+    ref = oracle.evaluate(ORC[name], (E, E, E), list(_stored(c, "f32")), x.astype(np.float64))
+    assert np.abs(f - ref).max() <= 2e-6
+
+
+def test_constant_and_linear_reproduction_at_full_size(device):
+    """Closed forms at the bench's full size (BCC 2x64^3, 2^22 points):
+    c = 1 gives f = 1 and c_n = a . n + b gives f(x) = a . x + b exactly
+    (partition of unity and linear reproduction of the centred spline)."""
+    print("case reproduction full size", flush=True)
+    E = 64
+    pos = inputs.site_positions("bcc8", E).astype(np.float64)
+    a = np.array([0.01, -0.02, 0.005])
+    c = pos @ a + 0.25
+    vol = _mk("bcc8", E, c, "f32", device)
+    x = inputs.uniform_points(2, "bcc8", E, 1 << 22)
+    xt = torch.tensor(x, device=device)
+    f = vol.eval(xt).double().cpu().numpy()
+    exact = x.astype(np.float64) @ a + 0.25
+    assert np.abs(f - exact).max() <= 2e-6 * np.abs(c).max()
+
+
+@pytest.mark.parametrize("wl", [1, 2, 3])
+def test_full_size_workloads_sampled(device, wl):
+    """The bench workloads at full size, in the bench's launch configuration;
+    a seeded sample of outputs is checked against the checker point by point."""
+    print("case workload", wl, flush=True)
+    w = {1: inputs.workload1, 2: inputs.workload2, 3: inputs.workload3}[wl]()
+    name, E, c, x = w["spline"], w["E"], w["coeffs"], w["points"]
+    vol = _mk(name, E, c, "f32", device)
+    f = vol.eval(torch.tensor(x, device=device)).cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(wl)
+    idx = rng.choice(x.shape[0], 1500, replace=False)
+    cs = _stored(c, "f32")
+    ref = oracle.evaluate(ORC[name], (E, E, E), list(cs), x[idx].astype(np.float64))
+    assert np.abs(f[idx] - ref).max() <= 2e-6 * np.abs(cs).max()
+    assert np.isfinite(f).all()
