@@ -1,11 +1,300 @@
-// dL/dc pass (not yet implemented).
+// dL/dc of the convolution sum without floating-point atomics:
+//
+//   dL/dc_n = sum_i g_i phi(x_i - n)
+//
+// Each point only touches the stencil of its region of evaluation, so the
+// pass is organised around ROE cells (the lattice point k of Algorithm 1):
+//   1. key every point by its cell (inactive points get a sentinel key);
+//   2. stable radix sort of (cell, point index)   -- a library sort;
+//   3. cell start offsets by lower-bound search on the sorted keys;
+//   4. per sorted point, the weights g_i w_j(y_i) of every union tap j (the
+//      per-tap polynomials of the reference sub-region) and its symmetry id;
+//   5. per stored site n, a gather over the cells n - v for every offset v of
+//      the symmetry-closed stencil U, in a fixed order: a point of cell
+//      n - v with symmetry element G reaches n through the tap j with
+//      G^T o_j = v (generated table J[G][v]).
+// The summation order is fixed by the sorted point order and the order of U,
+// so the result is bit-reproducible.
 #include <hip/hip_runtime.h>
 
+#include <string.h>
+
+#include <rocprim/device/device_radix_sort.hpp>
+
 #include "lsp_backward.h"
+#include "lsp_kernels.h"
 
 namespace lsp {
 
-size_t backward_workspace_bytes(int, int, const int64_t*, int, int64_t) { return 0; }
-hipError_t launch_backward_coef(const BackwardArgs&) { return hipErrorNotSupported; }
+namespace {
+
+constexpr int kBlk = 256;
+
+template <int KIND> struct BwdTraits;
+template <> struct BwdTraits<kTricubic> { static constexpr int D = 1; };
+template <> struct BwdTraits<kBcc8> { static constexpr int D = 2; };
+template <> struct BwdTraits<kFcc6> { static constexpr int D = 2; };
+
+// Cell grid: the padded per-coset grid of the coefficient layout, one cell
+// per lattice point, cell = coset * NC + ((K_z + pad) * PY + K_y + pad) * PX + K_x + pad
+// with K = floor(k / D).
+struct CellGeom {
+    int PX, PY, PZ, NC;
+    int pad;
+    int ncell;
+};
+
+template <int KIND>
+__host__ __device__ __forceinline__ int coset_of(int p0, int p1, int p2) {
+    if (KIND == kTricubic) return 0;
+    if (KIND == kBcc8) return p0;
+    return fcc_coset(p0 | (p1 << 1) | (p2 << 2));
+}
+
+template <int KIND>
+__device__ __forceinline__ int cell_of(const int k[3], const CellGeom& cg) {
+    constexpr int D = BwdTraits<KIND>::D;
+    const int K0 = D == 1 ? k[0] : (k[0] >> 1);
+    const int K1 = D == 1 ? k[1] : (k[1] >> 1);
+    const int K2 = D == 1 ? k[2] : (k[2] >> 1);
+    const int m = coset_of<KIND>(k[0] & 1, k[1] & 1, k[2] & 1);
+    return m * cg.NC + ((K2 + cg.pad) * cg.PY + (K1 + cg.pad)) * cg.PX + (K0 + cg.pad);
+}
+
+template <int KIND, class PT>
+__global__ __launch_bounds__(kBlk) void k_bin_keys(const PT* __restrict__ pts, int N, VolGeom g,
+                                                   CellGeom cg, int* __restrict__ keys,
+                                                   int* __restrict__ vals) {
+    const int i = blockIdx.x * kBlk + threadIdx.x;
+    if (i >= N) return;
+    PT x[3];
+    load_point(pts, i, x);
+    Loc L;
+    locate<KIND>(x, g, L);
+    keys[i] = L.active ? cell_of<KIND>(L.k, cg) : cg.ncell;
+    vals[i] = i;
+}
+
+// off[c] = first sorted position whose key is >= c, for c in [0, ncell].
+__global__ __launch_bounds__(kBlk) void k_cell_offsets(const int* __restrict__ keys, int N,
+                                                       int ncell, int* __restrict__ off) {
+    const int stride = gridDim.x * kBlk;
+    for (int c = blockIdx.x * kBlk + threadIdx.x; c <= ncell; c += stride) {
+        int lo = 0, hi = N;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (keys[mid] < c) lo = mid + 1;
+            else hi = mid;
+        }
+        off[c] = lo;
+    }
+}
+
+template <int KIND>
+__device__ __forceinline__ void tap_weights(const Loc& L, float* w) {
+    if (KIND == kTricubic) {
+        gen::tricubic_weights_r0(L.y[0], L.y[1], L.y[2], w);
+    } else if (KIND == kBcc8) {
+        gen::bcc8_weights_r0(L.y[0], L.y[1], L.y[2], w);
+    } else {
+        if (L.region) gen::fcc6_weights_r1(L.y[0], L.y[1], L.y[2], w);
+        else gen::fcc6_weights_r0(L.y[0], L.y[1], L.y[2], w);
+    }
+}
+
+template <int KIND, class PT>
+__global__ __launch_bounds__(kBlk) void k_point_weights(const PT* __restrict__ pts,
+                                                        const int* __restrict__ skeys,
+                                                        const int* __restrict__ svals, int N,
+                                                        int ncell, VolGeom g,
+                                                        const float* __restrict__ gin,
+                                                        float* __restrict__ W,
+                                                        unsigned char* __restrict__ sym) {
+    using T = typename Tables<KIND>::T;
+    const int p = blockIdx.x * kBlk + threadIdx.x;
+    if (p >= N) return;
+    if (skeys[p] >= ncell) return;  // inactive: never read by the gather
+    const int i = svals[p];
+    PT x[3];
+    load_point(pts, i, x);
+    Loc L;
+    locate<KIND>(x, g, L);
+    float w[T::kTaps];
+    tap_weights<KIND>(L, w);
+    const float gi = gin[i];
+    float* row = W + (size_t)p * T::kTaps;
+#pragma unroll
+    for (int j = 0; j < T::kTaps; ++j) row[j] = gi * w[j];
+    sym[p] = (unsigned char)sym_id<KIND>(L);
+}
+
+template <int KIND>
+__global__ __launch_bounds__(kBlk) void k_gather_coef(const int* __restrict__ off,
+                                                      const unsigned char* __restrict__ sym,
+                                                      const float* __restrict__ W, CellGeom cg,
+                                                      int X, int Y, int Z, int n_cosets,
+                                                      float* __restrict__ dL_dc) {
+    using T = typename Tables<KIND>::T;
+    constexpr int D = BwdTraits<KIND>::D;
+    __shared__ signed char J[T::kNumSym * T::kNumU];
+    for (int t = threadIdx.x; t < T::kNumSym * T::kNumU; t += kBlk)
+        J[t] = T::kJ[t / T::kNumU][t % T::kNumU];
+    __syncthreads();
+    const long long per = (long long)X * Y * Z;
+    const long long s = (long long)blockIdx.x * kBlk + threadIdx.x;
+    if (s >= per * n_cosets) return;
+    const int m = (int)(s / per);
+    const long long r = s - (long long)m * per;
+    const int ix = (int)(r % X);
+    const int iy = (int)((r / X) % Y);
+    const int iz = (int)(r / ((long long)X * Y));
+    // lattice position of the site: D * idx + shift_m
+    int sh0 = 0, sh1 = 0, sh2 = 0;
+    if (KIND == kBcc8) { sh0 = sh1 = sh2 = m; }
+    if (KIND == kFcc6) {
+        sh0 = (m == 1 || m == 2) ? 1 : 0;
+        sh1 = (m == 1 || m == 3) ? 1 : 0;
+        sh2 = (m == 2 || m == 3) ? 1 : 0;
+    }
+    const int n0 = D * ix + sh0, n1 = D * iy + sh1, n2 = D * iz + sh2;
+    float acc = 0.0f;
+    for (int u = 0; u < T::kNumU; ++u) {
+        const int c0 = n0 - T::kU[u][0], c1 = n1 - T::kU[u][1], c2 = n2 - T::kU[u][2];
+        const int K0 = D == 1 ? c0 : (c0 >> 1);
+        const int K1 = D == 1 ? c1 : (c1 >> 1);
+        const int K2 = D == 1 ? c2 : (c2 >> 1);
+        if (K0 < -cg.pad || K0 >= cg.PX - cg.pad || K1 < -cg.pad || K1 >= cg.PY - cg.pad ||
+            K2 < -cg.pad || K2 >= cg.PZ - cg.pad)
+            continue;
+        const int cm = coset_of<KIND>(c0 & 1, c1 & 1, c2 & 1);
+        const int cell = cm * cg.NC + ((K2 + cg.pad) * cg.PY + (K1 + cg.pad)) * cg.PX + (K0 + cg.pad);
+        const int b = off[cell], e = off[cell + 1];
+        for (int p = b; p < e; ++p) {
+            const int j = J[(int)sym[p] * T::kNumU + u];
+            if (j >= 0) acc += W[(size_t)p * T::kTaps + j];
+        }
+    }
+    dL_dc[s] = acc;
+}
+
+struct Layout {
+    size_t keys_in, vals_in, keys_out, vals_out, off, sym, W, tmp, total;
+    size_t tmp_bytes;
+};
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+int taps_of(int kind) {
+    if (kind == kTricubic) return gen::tricubic_tables::kTaps;
+    if (kind == kBcc8) return gen::bcc8_tables::kTaps;
+    return gen::fcc6_tables::kTaps;
+}
+
+CellGeom cell_geom(const int dims[3], int pad, int n_cosets) {
+    CellGeom cg{};
+    cg.PX = dims[0] + 2 * pad;
+    cg.PY = dims[1] + 2 * pad;
+    cg.PZ = dims[2] + 2 * pad;
+    cg.NC = cg.PX * cg.PY * cg.PZ;
+    cg.pad = pad;
+    cg.ncell = cg.NC * n_cosets;
+    return cg;
+}
+
+int key_bits(int ncell) {
+    int b = 1;
+    while (b < 31 && (1ll << b) <= ncell) ++b;
+    return b;
+}
+
+bool layout(int kind, int n_cosets, const int dims[3], int pad, long long N, Layout* L) {
+    const CellGeom cg = cell_geom(dims, pad, n_cosets);
+    size_t tmp = 0;
+    const unsigned n = (unsigned)(N > 0 ? N : 1);
+    if (rocprim::radix_sort_pairs(nullptr, tmp, (int*)nullptr, (int*)nullptr, (int*)nullptr,
+                                  (int*)nullptr, n, 0, key_bits(cg.ncell)) != hipSuccess)
+        return false;
+    size_t o = 0;
+    const size_t nb = align256(sizeof(int) * (size_t)n);
+    L->keys_in = o; o += nb;
+    L->vals_in = o; o += nb;
+    L->keys_out = o; o += nb;
+    L->vals_out = o; o += nb;
+    L->off = o; o += align256(sizeof(int) * ((size_t)cg.ncell + 1));
+    L->sym = o; o += align256((size_t)n);
+    L->W = o; o += align256(sizeof(float) * (size_t)n * taps_of(kind));
+    L->tmp = o; o += align256(tmp);
+    L->tmp_bytes = tmp;
+    L->total = o;
+    return true;
+}
+
+template <int KIND, class PT>
+hipError_t run(const BackwardArgs& a, const Layout& ly) {
+    using T = typename Tables<KIND>::T;
+    char* ws = static_cast<char*>(a.ws);
+    int* keys_in = reinterpret_cast<int*>(ws + ly.keys_in);
+    int* vals_in = reinterpret_cast<int*>(ws + ly.vals_in);
+    int* keys_out = reinterpret_cast<int*>(ws + ly.keys_out);
+    int* vals_out = reinterpret_cast<int*>(ws + ly.vals_out);
+    int* off = reinterpret_cast<int*>(ws + ly.off);
+    unsigned char* sym = reinterpret_cast<unsigned char*>(ws + ly.sym);
+    float* W = reinterpret_cast<float*>(ws + ly.W);
+    const CellGeom cg = cell_geom(a.dims, a.g.pad, a.n_cosets);
+    const int N = a.N;
+    const PT* pts = static_cast<const PT*>(a.pts);
+    const int nblk = (N + kBlk - 1) / kBlk;
+    if (N > 0) {
+        hipLaunchKernelGGL((k_bin_keys<KIND, PT>), dim3(nblk), dim3(kBlk), 0, a.stream, pts, N, a.g,
+                           cg, keys_in, vals_in);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        size_t tmp = ly.tmp_bytes;
+        e = rocprim::radix_sort_pairs(ws + ly.tmp, tmp, keys_in, keys_out, vals_in, vals_out,
+                                      (unsigned)N, 0, key_bits(cg.ncell), a.stream);
+        if (e != hipSuccess) return e;
+    }
+    {
+        long long blocks = ((long long)cg.ncell + 1 + kBlk - 1) / kBlk;
+        if (blocks > 65536) blocks = 65536;
+        hipLaunchKernelGGL(k_cell_offsets, dim3((unsigned)blocks), dim3(kBlk), 0, a.stream, keys_out,
+                           N, cg.ncell, off);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (N > 0) {
+        hipLaunchKernelGGL((k_point_weights<KIND, PT>), dim3(nblk), dim3(kBlk), 0, a.stream, pts,
+                           keys_out, vals_out, N, cg.ncell, a.g, a.dL_df, W, sym);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const long long sites = (long long)a.dims[0] * a.dims[1] * a.dims[2] * a.n_cosets;
+    const long long gblocks = (sites + kBlk - 1) / kBlk;
+    hipLaunchKernelGGL((k_gather_coef<KIND>), dim3((unsigned)gblocks), dim3(kBlk), 0, a.stream, off,
+                       sym, W, cg, a.dims[0], a.dims[1], a.dims[2], a.n_cosets, a.dL_dc);
+    (void)sizeof(T);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t backward_workspace_bytes(int kind, int n_cosets, const int64_t dims[3], int pad, int64_t N) {
+    const int d[3] = {(int)dims[0], (int)dims[1], (int)dims[2]};
+    Layout ly{};
+    if (!layout(kind, n_cosets, d, pad, N, &ly)) return (size_t)-1;
+    return ly.total;
+}
+
+hipError_t launch_backward_coef(const BackwardArgs& a) {
+    Layout ly{};
+    if (!layout(a.kind, a.n_cosets, a.dims, a.g.pad, a.N, &ly)) return hipErrorInvalidValue;
+    if (a.ws_bytes < ly.total) return hipErrorInvalidValue;
+    switch (a.kind) {
+        case kTricubic: return a.pts_f64 ? run<kTricubic, double>(a, ly) : run<kTricubic, float>(a, ly);
+        case kBcc8: return a.pts_f64 ? run<kBcc8, double>(a, ly) : run<kBcc8, float>(a, ly);
+        case kFcc6: return a.pts_f64 ? run<kFcc6, double>(a, ly) : run<kFcc6, float>(a, ly);
+    }
+    return hipErrorInvalidValue;
+}
 
 }  // namespace lsp

@@ -438,8 +438,10 @@ lsp_status lsp_eval_grad(const lsp_volume* vol, const void* pts, lsp_dtype pts_d
 lsp_status lsp_backward_workspace_size(const lsp_volume* vol, int64_t N, size_t* bytes) {
     if (!vol || !bytes) return fail(LSP_E_INVALID_ARG, "NULL argument");
     if (N < 0 || N >= ((int64_t)1 << 31)) return fail(LSP_E_SHAPE, "N = %lld out of [0, 2^31)", (long long)N);
-    *bytes = lsp::backward_workspace_bytes(vol->def.kind, vol->def.n_cosets, vol->dims, vol->def.pad,
-                                           N);
+    const size_t b = lsp::backward_workspace_bytes(vol->def.kind, vol->def.n_cosets, vol->dims,
+                                                   vol->def.pad, N);
+    if (b == (size_t)-1) return fail(LSP_E_HIP, "sort workspace query failed");
+    *bytes = b;
     return LSP_OK;
 }
 
@@ -456,6 +458,7 @@ lsp_status lsp_backward(const lsp_volume* vol, const void* pts, lsp_dtype pts_dt
     if (dL_dc) {
         const size_t need = lsp::backward_workspace_bytes(vol->def.kind, vol->def.n_cosets, vol->dims,
                                                           vol->def.pad, N);
+        if (need == (size_t)-1) return fail(LSP_E_HIP, "sort workspace query failed");
         if (need > 0 && (!workspace || ws_bytes < need))
             return fail(LSP_E_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
         if (((uintptr_t)workspace & 255) != 0)

@@ -41,6 +41,7 @@ struct Loc {
     int axis[3];       // global axis of each reference axis
     float sgn[3];      // sign of each reference axis (reflection)
     int region;        // reference sub-region (polynomial) index
+    int k[3];          // the ROE lattice point (origin for inactive points)
     bool active;       // some stencil tap lies in the stored lattice
     bool nan;          // a coordinate was NaN
 };
@@ -76,7 +77,20 @@ LSP_HD void finish_common(const PT x[3], const PT k[3], const VolGeom& g, Loc& L
         // lattice here) so that every fetch stays inside the buffer
         d[a] = act ? (float)(x[a] - k[a]) : 0.0f;
         if (!act) ki[a] = 0;
+        L.k[a] = ki[a];
     }
+}
+
+// Symmetry element of a located point in the encoding of the generated
+// transposed-stencil tables: 0 without symmetry; the sign bits (bit r set when
+// reference axis r is reflected) for reflections only; and
+// (axis[0] * 3 + axis[1]) * 8 + sign bits for signed permutations.
+template <int KIND>
+LSP_HD int sym_id(const Loc& L) {
+    if (KIND == kTricubic) return 0;
+    const int bits = (L.sgn[0] < 0.0f ? 1 : 0) | (L.sgn[1] < 0.0f ? 2 : 0) | (L.sgn[2] < 0.0f ? 4 : 0);
+    if (KIND == kFcc6) return bits;
+    return (L.axis[0] * 3 + L.axis[1]) * 8 + bits;
 }
 
 // Tensor-product cubic on Z^3: parallelepiped ROE [0,1)^3 via floor, one

@@ -81,6 +81,44 @@ def choose_frame(d: Derived, region: Region, max_cond=6.5):
     return best[1], best[2], best[3]
 
 
+# ----------------------------------------------------------- symmetry group
+
+def symmetry_elements(symmetry: str):
+    """(sym id, axis, sgn) for every element G of the symmetry used to reach the
+    reference sub-region, in the encoding the device code uses: reference axis r
+    maps to global axis axis[r] with sign sgn[r], so (G^T o)[axis[r]] =
+    sgn[r] * o[r]; sym id = (axis[0] * 3 + axis[1]) * 8 + (bits of sgn < 0)."""
+    out = []
+    perms = [(0, 1, 2)] if symmetry in ("none", "signs") else list(itertools.permutations(range(3)))
+    signs = [(1, 1, 1)] if symmetry == "none" else list(itertools.product((1, -1), repeat=3))
+    for ax in perms:
+        for sg in signs:
+            bits = sum(1 << r for r in range(3) if sg[r] < 0)
+            sid = bits if symmetry != "signed_perm" else (ax[0] * 3 + ax[1]) * 8 + bits
+            out.append((sid, ax, sg))
+    return out
+
+
+def transposed_stencil(union, symmetry: str):
+    """U: every global offset G^T o_j over the group and the union stencil
+    (sorted z, y, x); J[sym][u]: the union tap j with G^T o_j = U[u], or -1."""
+    els = symmetry_elements(symmetry)
+    vs = set()
+    img = {}
+    for sid, ax, sg in els:
+        for j, o in enumerate(union):
+            v = [0, 0, 0]
+            for r in range(3):
+                v[ax[r]] = sg[r] * o[r]
+            v = tuple(v)
+            vs.add(v)
+            img[(sid, v)] = j
+    U = sorted(vs, key=lambda v: (v[2], v[1], v[0]))
+    nsym = 1 if symmetry == "none" else (8 if symmetry == "signs" else 72)
+    J = [[img.get((sid, v), -1) for v in U] for sid in range(nsym)]
+    return U, J
+
+
 # ----------------------------------------------------------- code helpers
 
 def horner(terms: Dict[Tuple[int, ...], str], nvars: int, names: Sequence[str]) -> str:
@@ -210,6 +248,7 @@ class SplineCode:
             "radius": max(abs(v) for o in self.union for v in o),
             "tensor": self.tensor is not None,
             "regions": regs,
+            "transposed": dict(zip(("U", "J"), transposed_stencil(self.union, spec.symmetry))),
         }
 
     # -- counts
@@ -263,6 +302,14 @@ class SplineCode:
         for k, d in enumerate(self.regions):
             mask = sum(1 << self.union.index(o) for o in d.taps)
             L.append("  static constexpr unsigned long long kRegionMask%d = 0x%xull;" % (k, mask))
+        U, J = transposed_stencil(self.union, spec.symmetry)
+        L.append("  // transposed stencil: every offset G^T o_j over the symmetry group, and the")
+        L.append("  // union tap j that lands there for each symmetry element (-1: none)")
+        L.append("  static constexpr int kNumU = %d;" % len(U))
+        L.append("  static constexpr int kNumSym = %d;" % len(J))
+        L.append("  static constexpr signed char kU[kNumU][3] = {%s};" % ", ".join("{%d, %d, %d}" % v for v in U))
+        L.append("  static constexpr signed char kJ[kNumSym][kNumU] = {%s};" % ", ".join(
+            "{%s}" % ", ".join(str(j) for j in row) for row in J))
         L.append("};")
         L.append("")
         if self.tensor is not None:

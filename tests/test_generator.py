@@ -97,3 +97,37 @@ def test_committed_headers_are_current(tmp_path):
         for ext in (".h", ".json"):
             with open(os.path.join(OUT_DIR, nm + ext)) as a, open(os.path.join(tmp_path, nm + ext)) as b:
                 assert a.read() == b.read(), nm + ext
+
+
+@pytest.mark.parametrize("name", ["tricubic", "bcc8", "fcc6"])
+def test_transposed_stencil_tables(name):
+    """Every tap j of a located point reaches the site K + G^T o_j, and the
+    transposed table maps (G, K + G^T o_j - K) back to exactly that j."""
+    tab = interp.load_tables(name)
+    U = [tuple(v) for v in tab["transposed"]["U"]]
+    J = tab["transposed"]["J"]
+    union = np.array(tab["union"])
+    uidx = {v: i for i, v in enumerate(U)}
+    x = rng.uniform(5, 12, (400, 3))
+    K, y, G, region = interp.locate(tab, x)
+    for i in range(x.shape[0]):
+        Gi = G[i]
+        if tab["symmetry"] == "none":
+            sid = 0
+        else:
+            # reference axis r -> global axis a with G[r, a] = +-1
+            ax = [int(np.nonzero(Gi[r])[0][0]) for r in range(3)]
+            bits = sum(1 << r for r in range(3) if Gi[r, ax[r]] < 0)
+            sid = bits if tab["symmetry"] == "signs" else (ax[0] * 3 + ax[1]) * 8 + bits
+        for j, o in enumerate(union):
+            v = tuple(int(round(t)) for t in Gi.T @ o)
+            assert J[sid][uidx[v]] == j
+    # a symmetry element maps distinct taps to distinct offsets (ids that
+    # encode no group element have empty rows)
+    n_el = 0
+    for row in J:
+        hit = [j for j in row if j >= 0]
+        if hit:
+            n_el += 1
+            assert sorted(hit) == list(range(len(union)))
+    assert n_el == {"none": 1, "signs": 8, "signed_perm": 48}[tab["symmetry"]]

@@ -1,0 +1,183 @@
+"""GPU parity of the backward pass (dL/dc by the transposed-stencil gather,
+dL/dx by the gradient kernel) against the FP64 CPU checker, plus
+determinism, sum rules, autograd, finite differences and a small fit.
+
+dL/dc tolerance: |dc_gpu - dc_ref|_n <= 1e-5 * sum_i |g_i| phi(x_i - n)
++ 1e-12 (FP32 products and sums of non-negative weights)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2102_08518_amd import api, inputs
+
+pytestmark = pytest.mark.gpu
+
+ORC = {"tricubic": oracle.TRICUBIC, "bcc8": oracle.BCC8, "fcc6": oracle.FCC6}
+
+
+def _setup(name, E, n, seed, dev, outside=True):
+    rng = np.random.default_rng(seed)
+    nc = ORC[name].n_cosets
+    c = rng.uniform(-1, 1, (nc, E, E, E)).astype(np.float32)
+    D = inputs.LATTICE[name]["D"]
+    hi = D * (E - 1) + 1
+    x = (rng.uniform(-3, hi + 3, (n, 3)) if outside
+         else rng.uniform(*inputs.interior(name, E), (n, 3))).astype(np.float32)
+    g = rng.normal(size=n).astype(np.float32)
+    vol = api.Volume(getattr(api.Spline, name)(), (E, E, E), "f32")
+    vol.set(torch.tensor(c, device=dev))
+    return vol, c, x, g
+
+
+@pytest.mark.parametrize("name", ["tricubic", "bcc8", "fcc6"])
+def test_dLdc_matches_oracle(device, name):
+    print("case dLdc", name, flush=True)
+    E = 9
+    vol, c, x, g = _setup(name, E, 2999, 31, device)
+    xt = torch.tensor(x, device=device)
+    gt = torch.tensor(g, device=device)
+    dc, dx = vol.backward(xt, gt, want_dc=True, want_dx=True)
+    dc = dc.cpu().numpy().astype(np.float64)
+    xs = x.astype(np.float64)
+    ref = np.stack(oracle.backward(ORC[name], (E, E, E), xs, g.astype(np.float64)))
+    scale = np.stack(oracle.backward(ORC[name], (E, E, E), xs, np.abs(g).astype(np.float64)))
+    assert np.all(np.abs(dc - ref) <= 1e-5 * scale + 1e-12), np.abs(dc - ref).max()
+    _, gref = oracle.evaluate(ORC[name], (E, E, E), list(c.astype(np.float64)), xs, grad=True)
+    np.testing.assert_allclose(dx.cpu().numpy(), g[:, None] * gref, rtol=0,
+                               atol=2e-5 * np.abs(g).max())
+
+
+@pytest.mark.parametrize("name", ["bcc8", "fcc6"])
+def test_dLdc_deterministic_and_sum_rules(device, name):
+    """Two runs give bit-identical dL/dc; for interior points
+    sum_n dL/dc_n = sum_i g_i and sum_n n dL/dc_n = sum_i g_i x_i
+    (partition of unity and linear reproduction)."""
+    print("case determinism", name, flush=True)
+    E = 16
+    vol, c, x, g = _setup(name, E, 200000, 32, device, outside=False)
+    xt = torch.tensor(x, device=device)
+    gt = torch.tensor(g, device=device)
+    a, _ = vol.backward(xt, gt, want_dx=False)
+    b, _ = vol.backward(xt, gt, want_dx=False)
+    assert torch.equal(a, b)
+    dc = a.double().cpu().numpy()
+    pos = inputs.site_positions(name, E).astype(np.float64)
+    gs = g.astype(np.float64)
+    tot = np.abs(gs).sum()
+    assert abs(dc.sum() - gs.sum()) <= 1e-5 * tot
+    mom = (dc[..., None] * pos).reshape(-1, 3).sum(0)
+    np.testing.assert_allclose(mom, (gs[:, None] * x.astype(np.float64)).sum(0), rtol=0,
+                               atol=1e-5 * tot * pos.max())
+
+
+def test_permuted_points_give_the_same_dLdc(device):
+    """Permuting the input points changes only the summation order within
+    a cell, so dL/dc agrees to rounding."""
+    print("case permutation", flush=True)
+    E = 10
+    vol, c, x, g = _setup("bcc8", E, 50000, 33, device, outside=False)
+    p = np.random.default_rng(0).permutation(x.shape[0])
+    a, _ = vol.backward(torch.tensor(x, device=device), torch.tensor(g, device=device), want_dx=False)
+    b, _ = vol.backward(torch.tensor(x[p], device=device), torch.tensor(g[p], device=device),
+                        want_dx=False)
+    np.testing.assert_allclose(a.cpu().numpy(), b.cpu().numpy(), rtol=1e-4, atol=1e-4)
+
+
+def test_autograd_and_finite_differences(device):
+    """LatticeSplineFn: dL/dc and dL/dx of an MSE loss match central finite
+    differences (step 1e-3) of the GPU forward itself."""
+    print("case autograd", flush=True)
+    E = 8
+    rng = np.random.default_rng(34)
+    c0 = rng.uniform(-1, 1, (2, E, E, E)).astype(np.float32)
+    x0 = rng.uniform(*inputs.interior("bcc8", E), (512, 3)).astype(np.float32)
+    y = rng.normal(size=512).astype(np.float32)
+    vol = api.Volume(api.Spline.bcc8(), (E, E, E), "f32")
+    c = torch.tensor(c0, device=device, requires_grad=True)
+    x = torch.tensor(x0, device=device, requires_grad=True)
+    yt = torch.tensor(y, device=device)
+    f = api.LatticeSplineFn.apply(x, c, vol)
+    loss = ((f - yt) ** 2).mean()
+    loss.backward()
+
+    def L(cc, xx):
+        with torch.no_grad():
+            vol.set(cc)
+            return float(((vol.eval(xx).double() - yt.double()) ** 2).mean())
+
+    h = 1e-3
+    cd = c.detach().clone()
+    for flat in rng.choice(c0.size, 6, replace=False):
+        idx = np.unravel_index(flat, c0.shape)
+        cp, cm = cd.clone(), cd.clone()
+        cp[idx] += h
+        cm[idx] -= h
+        fd = (L(cp, x.detach()) - L(cm, x.detach())) / (2 * h)
+        assert abs(fd - float(c.grad[idx])) <= 2e-3 * (abs(fd) + 1e-4), (idx, fd, float(c.grad[idx]))
+    xd = x.detach().clone()
+    for i in rng.choice(512, 4, replace=False):
+        for a in range(3):
+            xp, xm = xd.clone(), xd.clone()
+            xp[i, a] += h
+            xm[i, a] -= h
+            fd = (L(cd, xp) - L(cd, xm)) / (2 * h)
+            assert abs(fd - float(x.grad[i, a])) <= 5e-3 * abs(fd) + 1e-5, (i, a, fd)
+
+
+def _design_matrix(E, x):
+    """A[i, n] = phi(x_i - n) from the checker's phi over the candidate sites."""
+    pos = inputs.site_positions("bcc8", E).reshape(-1, 3).astype(np.float64)
+    r = 4.0
+    rows, cols, pts = [], [], []
+    for i in range(x.shape[0]):
+        near = np.nonzero(np.all(np.abs(pos - x[i]) < r, axis=1))[0]
+        rows.append(np.full(near.size, i))
+        cols.append(near)
+        pts.append(x[i] - pos[near])
+    rows, cols = np.concatenate(rows), np.concatenate(cols)
+    vals = oracle.phi(oracle.BCC8, np.concatenate(pts))
+    A = np.zeros((x.shape[0], pos.shape[0]))
+    A[rows, cols] = vals
+    return A
+
+
+def test_adam_fit_matches_fp64_fit(device):
+    """Fit BCC coefficients (2 x 8^3) to 4000 samples of a smooth field with
+    200 Adam steps; the loss curve agrees with an FP64 Adam driven by the
+    checker's phi within 1e-3 relative."""
+    print("case adam fit", flush=True)
+    E = 8
+    lo, hi = inputs.interior("bcc8", E)
+    field = inputs.smooth_field(4, lo, hi)
+    x = np.random.default_rng(35).uniform(lo, hi, (4000, 3)).astype(np.float32)
+    y = field(x.astype(np.float64))
+    A = _design_matrix(E, x.astype(np.float64))
+    lr, b1, b2, eps = 0.05, 0.9, 0.999, 1e-8
+    c = np.zeros(A.shape[1])
+    m = np.zeros_like(c)
+    v = np.zeros_like(c)
+    ref_loss = []
+    for t in range(1, 201):
+        r = A @ c - y
+        ref_loss.append(float((r ** 2).mean()))
+        gr = A.T @ (2 * r / r.size)
+        m = b1 * m + (1 - b1) * gr
+        v = b2 * v + (1 - b2) * gr * gr
+        c -= lr * (m / (1 - b1 ** t)) / (np.sqrt(v / (1 - b2 ** t)) + eps)
+    vol = api.Volume(api.Spline.bcc8(), (E, E, E), "f32")
+    ct = torch.zeros(2, E, E, E, device=device, requires_grad=True)
+    opt = torch.optim.Adam([ct], lr=lr, betas=(b1, b2), eps=eps)
+    xt = torch.tensor(x, device=device)
+    yt = torch.tensor(y, dtype=torch.float32, device=device)
+    gpu_loss = []
+    for t in range(200):
+        opt.zero_grad()
+        f = api.LatticeSplineFn.apply(xt, ct, vol)
+        loss = ((f - yt) ** 2).mean()
+        loss.backward()
+        opt.step()
+        gpu_loss.append(float(loss))
+    gpu_loss, ref_loss = np.array(gpu_loss), np.array(ref_loss)
+    assert gpu_loss[-1] < 0.05 * gpu_loss[0]
+    np.testing.assert_allclose(gpu_loss, ref_loss, rtol=1e-3, atol=1e-7)
