@@ -208,9 +208,13 @@ lsp_status lsp_backward(const lsp_volume* vol, const void* pts, lsp_dtype pts_dt
  */
 lsp_status lsp_debug_tap_offsets(const lsp_spline* sp, const int64_t dims[3], lsp_dtype storage,
                                  const double* pts, int64_t N, int32_t* offs, int32_t* flags);
-/* Internal layout: out (host, 12 int32) = element, row, slice and coset
- * strides in bytes, halo, kmin[3], kmax[3], storage code; *nbytes = buffer
- * size in bytes. */
+/* Internal layout: out (host, 20 int32) = bytes per coefficient, halo,
+ * kmin[3], kmax[3] (range of ROE lattice points whose stencil reaches a
+ * stored site), log2 brick extent[3], brick stride[3] and in-brick site
+ * stride[3] in bytes, storage code, n_cosets, 0; *nbytes = buffer size in
+ * bytes.  The byte offset of coset m's site with index idx is
+ * m * es + sum_a ((i_a >> lb_a) * bs_a + (i_a & (2^lb_a - 1)) * is_a) with
+ * i = idx + halo. */
 lsp_status lsp_debug_geometry(const lsp_spline* sp, const int64_t dims[3], lsp_dtype storage,
                               int32_t* out, size_t* nbytes);
 

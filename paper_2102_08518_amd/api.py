@@ -89,15 +89,13 @@ class Spline:
 
     def debug_geometry(self, dims, storage: str = "f32"):
         d = (ctypes.c_int64 * 3)(*[int(v) for v in dims])
-        g = np.empty(12, dtype=np.int32)
+        g = np.empty(20, dtype=np.int32)
         nb = ctypes.c_size_t()
         N.check(N.lib().lsp_debug_geometry(self._h, d, _DT[storage], g.ctypes.data_as(N.i32p),
                                            ctypes.byref(nb)))
-        keys = ("sx", "sy", "sz", "scs", "pad", "kmin0", "kmin1", "kmin2", "kmax0", "kmax1",
-                "kmax2", "ctype")
-        out = dict(zip(keys, (int(v) for v in g)))
-        out["nbytes"] = nb.value
-        return out
+        v = [int(x) for x in g]
+        return dict(es=v[0], pad=v[1], kmin=v[2:5], kmax=v[5:8], lb=v[8:11], bs=v[11:14],
+                    is_=v[14:17], ctype=v[17], n_cosets=v[18], nbytes=nb.value)
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -8,13 +8,15 @@
 //   2. stable radix sort of (cell, point index)   -- a library sort;
 //   3. cell start offsets by lower-bound search on the sorted keys;
 //   4. per sorted point, the weights g_i w_j(y_i) of every union tap j (the
-//      per-tap polynomials of the reference sub-region) and its symmetry id;
-//   5. per stored site n, a gather over the cells n - v for every offset v of
-//      the symmetry-closed stencil U, in a fixed order: a point of cell
-//      n - v with symmetry element G reaches n through the tap j with
-//      G^T o_j = v (generated table J[G][v]).
-// The summation order is fixed by the sorted point order and the order of U,
-// so the result is bit-reproducible.
+//      per-tap polynomials of the reference sub-region), stored tap-major,
+//      and its symmetry id;
+//   5. per cell, partial sums P[u][cell] over the cell's points for every
+//      offset v_u of the symmetry-closed stencil U: a point with symmetry
+//      element G reaches the site cell + v_u through the tap j with
+//      G^T o_j = v_u (generated table J[G][u]);
+//   6. per stored site n, dL/dc_n = sum over u of P[u][n - v_u].
+// Every sum runs in a fixed order (sorted points, then U), so the result is
+// bit-reproducible.
 #include <hip/hip_runtime.h>
 
 #include <string.h>
@@ -122,24 +124,48 @@ __global__ __launch_bounds__(kBlk) void k_point_weights(const PT* __restrict__ p
     float w[T::kTaps];
     tap_weights<KIND>(L, w);
     const float gi = gin[i];
-    float* row = W + (size_t)p * T::kTaps;
 #pragma unroll
-    for (int j = 0; j < T::kTaps; ++j) row[j] = gi * w[j];
+    for (int j = 0; j < T::kTaps; ++j) W[(size_t)j * N + p] = gi * w[j];
     sym[p] = (unsigned char)sym_id<KIND>(L);
 }
 
+// P[u][cell] = sum over the cell's points p (sorted order) of W[J[sym_p][u]][p].
 template <int KIND>
-__global__ __launch_bounds__(kBlk) void k_gather_coef(const int* __restrict__ off,
-                                                      const unsigned char* __restrict__ sym,
-                                                      const float* __restrict__ W, CellGeom cg,
+__global__ __launch_bounds__(kBlk) void k_cell_partials(const int* __restrict__ off,
+                                                        const unsigned char* __restrict__ sym,
+                                                        const float* __restrict__ W, int N,
+                                                        int ncell, float* __restrict__ P) {
+    using T = typename Tables<KIND>::T;
+    constexpr int NU = T::kNumU;
+    __shared__ signed char J[T::kNumSym * NU];
+    for (int t = threadIdx.x; t < T::kNumSym * NU; t += kBlk) J[t] = T::kJ[t / NU][t % NU];
+    __syncthreads();
+    const int c = blockIdx.x * kBlk + threadIdx.x;
+    if (c >= ncell) return;
+    float acc[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) acc[u] = 0.0f;
+    const int b = off[c], e = off[c + 1];
+    for (int p = b; p < e; ++p) {
+        const signed char* row = J + (int)sym[p] * NU;
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            const int j = row[u];
+            if (j >= 0) acc[u] += W[(size_t)j * N + p];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < NU; ++u) P[(size_t)u * ncell + c] = acc[u];
+}
+
+// dL/dc_n = sum_u P[u][n - v_u], one thread per stored site in the canonical
+// coset-major C order of the output.
+template <int KIND>
+__global__ __launch_bounds__(kBlk) void k_site_gather(const float* __restrict__ P, CellGeom cg,
                                                       int X, int Y, int Z, int n_cosets,
                                                       float* __restrict__ dL_dc) {
     using T = typename Tables<KIND>::T;
     constexpr int D = BwdTraits<KIND>::D;
-    __shared__ signed char J[T::kNumSym * T::kNumU];
-    for (int t = threadIdx.x; t < T::kNumSym * T::kNumU; t += kBlk)
-        J[t] = T::kJ[t / T::kNumU][t % T::kNumU];
-    __syncthreads();
     const long long per = (long long)X * Y * Z;
     const long long s = (long long)blockIdx.x * kBlk + threadIdx.x;
     if (s >= per * n_cosets) return;
@@ -158,6 +184,7 @@ __global__ __launch_bounds__(kBlk) void k_gather_coef(const int* __restrict__ of
     }
     const int n0 = D * ix + sh0, n1 = D * iy + sh1, n2 = D * iz + sh2;
     float acc = 0.0f;
+#pragma unroll 4
     for (int u = 0; u < T::kNumU; ++u) {
         const int c0 = n0 - T::kU[u][0], c1 = n1 - T::kU[u][1], c2 = n2 - T::kU[u][2];
         const int K0 = D == 1 ? c0 : (c0 >> 1);
@@ -168,17 +195,13 @@ __global__ __launch_bounds__(kBlk) void k_gather_coef(const int* __restrict__ of
             continue;
         const int cm = coset_of<KIND>(c0 & 1, c1 & 1, c2 & 1);
         const int cell = cm * cg.NC + ((K2 + cg.pad) * cg.PY + (K1 + cg.pad)) * cg.PX + (K0 + cg.pad);
-        const int b = off[cell], e = off[cell + 1];
-        for (int p = b; p < e; ++p) {
-            const int j = J[(int)sym[p] * T::kNumU + u];
-            if (j >= 0) acc += W[(size_t)p * T::kTaps + j];
-        }
+        acc += P[(size_t)u * cg.ncell + cell];
     }
     dL_dc[s] = acc;
 }
 
 struct Layout {
-    size_t keys_in, vals_in, keys_out, vals_out, off, sym, W, tmp, total;
+    size_t keys_in, vals_in, keys_out, vals_out, off, sym, W, P, tmp, total;
     size_t tmp_bytes;
 };
 
@@ -188,6 +211,12 @@ int taps_of(int kind) {
     if (kind == kTricubic) return gen::tricubic_tables::kTaps;
     if (kind == kBcc8) return gen::bcc8_tables::kTaps;
     return gen::fcc6_tables::kTaps;
+}
+
+int nu_of(int kind) {
+    if (kind == kTricubic) return gen::tricubic_tables::kNumU;
+    if (kind == kBcc8) return gen::bcc8_tables::kNumU;
+    return gen::fcc6_tables::kNumU;
 }
 
 CellGeom cell_geom(const int dims[3], int pad, int n_cosets) {
@@ -223,6 +252,7 @@ bool layout(int kind, int n_cosets, const int dims[3], int pad, long long N, Lay
     L->off = o; o += align256(sizeof(int) * ((size_t)cg.ncell + 1));
     L->sym = o; o += align256((size_t)n);
     L->W = o; o += align256(sizeof(float) * (size_t)n * taps_of(kind));
+    L->P = o; o += align256(sizeof(float) * (size_t)cg.ncell * nu_of(kind));
     L->tmp = o; o += align256(tmp);
     L->tmp_bytes = tmp;
     L->total = o;
@@ -240,6 +270,7 @@ hipError_t run(const BackwardArgs& a, const Layout& ly) {
     int* off = reinterpret_cast<int*>(ws + ly.off);
     unsigned char* sym = reinterpret_cast<unsigned char*>(ws + ly.sym);
     float* W = reinterpret_cast<float*>(ws + ly.W);
+    float* P = reinterpret_cast<float*>(ws + ly.P);
     const CellGeom cg = cell_geom(a.dims, a.g.pad, a.n_cosets);
     const int N = a.N;
     const PT* pts = static_cast<const PT*>(a.pts);
@@ -268,10 +299,17 @@ hipError_t run(const BackwardArgs& a, const Layout& ly) {
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
+    {
+        const int cblocks = (cg.ncell + kBlk - 1) / kBlk;
+        hipLaunchKernelGGL((k_cell_partials<KIND>), dim3(cblocks), dim3(kBlk), 0, a.stream, off, sym,
+                           W, N, cg.ncell, P);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     const long long sites = (long long)a.dims[0] * a.dims[1] * a.dims[2] * a.n_cosets;
     const long long gblocks = (sites + kBlk - 1) / kBlk;
-    hipLaunchKernelGGL((k_gather_coef<KIND>), dim3((unsigned)gblocks), dim3(kBlk), 0, a.stream, off,
-                       sym, W, cg, a.dims[0], a.dims[1], a.dims[2], a.n_cosets, a.dL_dc);
+    hipLaunchKernelGGL((k_site_gather<KIND>), dim3((unsigned)gblocks), dim3(kBlk), 0, a.stream, P, cg,
+                       a.dims[0], a.dims[1], a.dims[2], a.n_cosets, a.dL_dc);
     (void)sizeof(T);
     return hipGetLastError();
 }

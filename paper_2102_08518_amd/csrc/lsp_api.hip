@@ -4,6 +4,7 @@
 
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -186,24 +187,57 @@ int ctype_of(lsp_dtype storage) {
 
 lsp_status fail(lsp_status st, const char* fmt, ...);
 
-// Internal layout of a volume: per-coset padded grids, strides in bytes, and
-// the range of ROE lattice points whose stencil reaches a stored site.
+// Brick extent (x, y, z) of the interleaved layout per spline and element
+// size: the shapes that minimise the 128-byte lines a random point's stencil
+// touches (one brick = one line).  LSP_BRICK="bx,by,bz" overrides them.
+void brick_dims(int kind, int es, int b[3]) {
+    static const int tab[3][2][3] = {
+        {{2, 4, 4}, {4, 4, 4}},   // tricubic: 4-byte, 2-byte coefficients
+        {{2, 2, 4}, {4, 4, 2}},   // BCC 8-direction (2 cosets per site)
+        {{2, 2, 2}, {2, 4, 2}},   // FCC 6-direction (4 cosets per site)
+    };
+    for (int a = 0; a < 3; ++a) b[a] = tab[kind][es == 4 ? 0 : 1][a];
+    const char* env = getenv("LSP_BRICK");
+    int v[3];
+    if (env && sscanf(env, "%d,%d,%d", &v[0], &v[1], &v[2]) == 3) {
+        bool ok = true;
+        for (int a = 0; a < 3; ++a) ok = ok && v[a] >= 1 && v[a] <= 64 && (v[a] & (v[a] - 1)) == 0;
+        if (ok)
+            for (int a = 0; a < 3; ++a) b[a] = v[a];
+    }
+}
+
+// Internal layout of a volume (interleaved cosets, bricks, zero halo) and the
+// range of ROE lattice points whose stencil reaches a stored site.
 lsp_status make_geom(const SplineDef& d, const int64_t dims[3], int ctype, lsp::VolGeom* out,
                      size_t* nbytes) {
     for (int a = 0; a < 3; ++a)
         if (dims[a] < 1 || dims[a] > (1 << 20))
             return fail(LSP_E_SHAPE, "dims[%d] = %lld out of [1, 2^20]", a, (long long)dims[a]);
     const int es = elem_size(ctype);
-    const i64 px = dims[0] + 2 * d.pad, py = dims[1] + 2 * d.pad, pz = dims[2] + 2 * d.pad;
-    const i64 total = px * py * pz * d.n_cosets * es;
+    int br[3];
+    brick_dims(d.kind, es, br);
+    const i64 site = (i64)d.n_cosets * es;
+    i64 nb[3];
+    for (int a = 0; a < 3; ++a) nb[a] = (dims[a] + 2 * d.pad + br[a] - 1) / br[a];
+    const i64 brick = (i64)br[0] * br[1] * br[2] * site;
+    const i64 total = nb[0] * nb[1] * nb[2] * brick;
     if (total >= ((i64)1 << 31))
         return fail(LSP_E_SHAPE, "padded coefficient buffer of %lld bytes exceeds 2^31", (long long)total);
     lsp::VolGeom g{};
-    g.sx = es;
-    g.sy = (int)(px * es);
-    g.sz = (int)(px * py * es);
-    g.scs = (int)(px * py * pz * es);
+    g.es = es;
     g.pad = d.pad;
+    for (int a = 0; a < 3; ++a) {
+        int l = 0;
+        while ((1 << l) < br[a]) ++l;
+        g.lb[a] = l;
+    }
+    g.is[0] = (int)site;
+    g.is[1] = (int)(br[0] * site);
+    g.is[2] = (int)(br[0] * br[1] * site);
+    g.bs[0] = (int)brick;
+    g.bs[1] = (int)(nb[0] * brick);
+    g.bs[2] = (int)(nb[0] * nb[1] * brick);
     for (int a = 0; a < 3; ++a) {
         int shmax = 0;
         for (int m = 0; m < d.n_cosets; ++m) shmax = std::max(shmax, d.shift[m][a]);
@@ -216,7 +250,6 @@ lsp_status make_geom(const SplineDef& d, const int64_t dims[3], int ctype, lsp::
     *nbytes = (size_t)total;
     return LSP_OK;
 }
-
 }  // namespace
 
 struct lsp_spline {
@@ -532,8 +565,9 @@ lsp_status lsp_debug_geometry(const lsp_spline* sp, const int64_t dims[3], lsp_d
     lsp::VolGeom g{};
     lsp_status st = make_geom(sp->def, dims, ctype, &g, nbytes);
     if (st) return st;
-    int v[12] = {g.sx, g.sy, g.sz, g.scs, g.pad, g.kmin[0], g.kmin[1], g.kmin[2],
-                 g.kmax[0], g.kmax[1], g.kmax[2], ctype};
+    int v[20] = {g.es, g.pad, g.kmin[0], g.kmin[1], g.kmin[2], g.kmax[0], g.kmax[1], g.kmax[2],
+                 g.lb[0], g.lb[1], g.lb[2], g.bs[0], g.bs[1], g.bs[2], g.is[0], g.is[1], g.is[2],
+                 ctype, sp->def.n_cosets, 0};
     memcpy(out, v, sizeof(v));
     return LSP_OK;
 }

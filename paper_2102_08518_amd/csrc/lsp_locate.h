@@ -3,13 +3,15 @@
 // coefficient fetches.  Written as __host__ __device__ so the host library can
 // run the same arithmetic for its bounds diagnostics.
 //
-// Internal coefficient layout: n_cosets arrays, each the per-coset grid
-// [z][y][x] surrounded by a zero halo of `pad` sites on every side.  Byte
-// offset of site idx in coset m:
-//     m*scs + (idx_z + pad)*sz + (idx_y + pad)*sy + (idx_x + pad)*sx
+// Internal coefficient layout: the per-coset grids, each surrounded by a zero
+// halo of `pad` sites, are interleaved (all cosets of one index idx are
+// adjacent) and cut into bricks of 2^lb[0] x 2^lb[1] x 2^lb[2] indices, so
+// that the few cache lines a stencil touches hold as many of its taps as
+// possible.  With i = idx + pad (non-negative), the byte offset of site idx
+// in coset m is separable per axis:
+//     m * es + sum_a f_a(i_a),   f_a(i) = (i >> lb[a]) * bs[a] + (i & (2^lb[a] - 1)) * is[a]
 // where idx = floor((n - shift_m) / D).  For D = 2 lattices floor(n/2)
-// equals (n - shift_m)/2 for the coset the site belongs to, so the coset only
-// selects the array.
+// equals (n - shift_m)/2 for the coset the site belongs to.
 #pragma once
 
 #include <stdint.h>
@@ -26,18 +28,27 @@ namespace lsp {
 
 enum Kind : int { kTricubic = 0, kBcc8 = 1, kFcc6 = 2 };
 
-// Geometry of one volume as the kernels see it.  All strides are in bytes.
+// Geometry of one volume as the kernels see it.  Strides are in bytes.
 struct VolGeom {
-    int sx, sy, sz, scs;    // element, row, slice and coset strides
+    int es;                 // bytes per coefficient
     int pad;                // halo in coset units
     int kmin[3], kmax[3];   // ROE lattice points k with any stored tap
+    int lb[3];              // log2 of the brick extent per axis
+    int bs[3];              // bytes between neighbouring bricks along each axis
+    int is[3];              // bytes between neighbouring sites inside a brick
 };
+
+LSP_HD int axis_term(int i, int lb, int bs, int is) {
+    return (i >> lb) * bs + (i & ((1 << lb) - 1)) * is;
+}
 
 // Result of locating one point.
 struct Loc {
     float y[3];        // coordinates in the reference sub-region frame
-    int base[4];       // byte offset of the stencil origin, per tap parity class
-    int S[3];          // signed byte stride of each reference axis
+    int bidx[2][3];    // padded index origin per reference axis, for even / odd offsets
+    int cb[4];         // coset byte offset per tap parity class
+    int s[3];          // +-1: reflection of each reference axis
+    int lb[3], bs[3], is[3];  // layout of the global axis behind each reference axis
     int axis[3];       // global axis of each reference axis
     float sgn[3];      // sign of each reference axis (reflection)
     int region;        // reference sub-region (polynomial) index
@@ -45,6 +56,15 @@ struct Loc {
     bool active;       // some stencil tap lies in the stored lattice
     bool nan;          // a coordinate was NaN
 };
+
+LSP_HD void set_axis_layout(const VolGeom& g, Loc& L) {
+    for (int r = 0; r < 3; ++r) {
+        const int a = L.axis[r];
+        L.lb[r] = a == 0 ? g.lb[0] : (a == 1 ? g.lb[1] : g.lb[2]);
+        L.bs[r] = a == 0 ? g.bs[0] : (a == 1 ? g.bs[1] : g.bs[2]);
+        L.is[r] = a == 0 ? g.is[0] : (a == 1 ? g.is[1] : g.is[2]);
+    }
+}
 
 // Coordinates are clamped to +-2^22 before rounding so the integer
 // conversions below stay defined; such points are outside any volume.
@@ -105,16 +125,15 @@ LSP_HD void locate_tricubic(const PT xin[3], const VolGeom& g, Loc& L) {
     int ki[3];
     float d[3];
     finish_common(x, k, g, L, ki, d);
-    const int st[3] = {g.sx, g.sy, g.sz};
-    int b = 0;
     for (int a = 0; a < 3; ++a) {
-        b += (ki[a] + g.pad) * st[a];
+        L.bidx[0][a] = L.bidx[1][a] = ki[a] + g.pad;
         L.y[a] = d[a];
-        L.S[a] = st[a];
+        L.s[a] = 1;
         L.axis[a] = a;
         L.sgn[a] = 1.0f;
     }
-    L.base[0] = L.base[1] = L.base[2] = L.base[3] = b;
+    L.cb[0] = L.cb[1] = L.cb[2] = L.cb[3] = 0;
+    set_axis_layout(g, L);
     L.region = 0;
 }
 
@@ -141,30 +160,28 @@ LSP_HD void locate_bcc(const PT xin[3], const VolGeom& g, Loc& L) {
     float d[3];
     finish_common(xr, k, g, L, ki, d);
     const int q = ki[0] & 1;
-    const int st[3] = {g.sx, g.sy, g.sz};
-    int be = q * g.scs, bo = (1 - q) * g.scs;
     float m[3];
-    int S[3], ax[3];
+    int b0[3], b1[3], ax[3];
     float sg[3];
     for (int a = 0; a < 3; ++a) {
         const int K = ki[a] >> 1;   // floor(k/2)
         const bool neg = d[a] < 0.0f;
-        be += (K + g.pad) * st[a];
-        bo += (K + g.pad + q - (neg ? 1 : 0)) * st[a];
+        b0[a] = K + g.pad;                          // even offsets: floor((k + s o)/2) = K + s o/2
+        b1[a] = K + g.pad + q - (neg ? 1 : 0);      // odd offsets:  K + q - [s < 0] + s floor(o/2)
         m[a] = neg ? -d[a] : d[a];
-        S[a] = neg ? -st[a] : st[a];
         sg[a] = neg ? -1.0f : 1.0f;
         ax[a] = a;
     }
-    // sorting network, descending by |d|, carrying the stride, axis, sign
+    // sorting network, descending by |d|, carrying the index origins, axis, sign
 #define LSP_CSWAP(i, j)                                                           \
     {                                                                             \
         const bool sw = m[i] < m[j];                                              \
         const float tm = sw ? m[j] : m[i], um = sw ? m[i] : m[j];                 \
-        const int tS = sw ? S[j] : S[i], uS = sw ? S[i] : S[j];                   \
+        const int t0 = sw ? b0[j] : b0[i], u0 = sw ? b0[i] : b0[j];               \
+        const int t1 = sw ? b1[j] : b1[i], u1 = sw ? b1[i] : b1[j];               \
         const int ta = sw ? ax[j] : ax[i], ua = sw ? ax[i] : ax[j];               \
         const float ts = sw ? sg[j] : sg[i], us = sw ? sg[i] : sg[j];             \
-        m[i] = tm; m[j] = um; S[i] = tS; S[j] = uS;                               \
+        m[i] = tm; m[j] = um; b0[i] = t0; b0[j] = u0; b1[i] = t1; b1[j] = u1;     \
         ax[i] = ta; ax[j] = ua; sg[i] = ts; sg[j] = us;                           \
     }
     LSP_CSWAP(0, 1)
@@ -173,13 +190,16 @@ LSP_HD void locate_bcc(const PT xin[3], const VolGeom& g, Loc& L) {
 #undef LSP_CSWAP
     for (int r = 0; r < 3; ++r) {
         L.y[r] = m[r];
-        L.S[r] = S[r];
+        L.bidx[0][r] = b0[r];
+        L.bidx[1][r] = b1[r];
         L.axis[r] = ax[r];
         L.sgn[r] = sg[r];
+        L.s[r] = sg[r] < 0.0f ? -1 : 1;
     }
-    L.base[0] = be;   // taps with all-even offsets
-    L.base[1] = bo;   // taps with all-odd offsets
-    L.base[2] = L.base[3] = be;
+    L.cb[0] = q * g.es;         // taps with all-even offsets stay in the coset of k
+    L.cb[1] = (1 - q) * g.es;   // taps with all-odd offsets are in the other coset
+    L.cb[2] = L.cb[3] = L.cb[0];
+    set_axis_layout(g, L);
     L.region = 0;
 }
 
@@ -218,26 +238,19 @@ LSP_HD void locate_fcc(const PT xin[3], const VolGeom& g, Loc& L) {
     float d[3];
     finish_common(xr, k, g, L, ki, d);
     const int q = (ki[0] & 1) | ((ki[1] & 1) << 1) | ((ki[2] & 1) << 2);
-    const int st[3] = {g.sx, g.sy, g.sz};
     const int pats[4] = {0, 3, 5, 6};
-    int common = 0;
-    int adj[3];
     for (int a = 0; a < 3; ++a) {
         const bool neg = d[a] < 0.0f;
-        common += ((ki[a] >> 1) + g.pad) * st[a];
-        adj[a] = (((q >> a) & 1) - (neg ? 1 : 0)) * st[a];
+        const int K = ki[a] >> 1;
+        L.bidx[0][a] = K + g.pad;                                   // even component of o
+        L.bidx[1][a] = K + g.pad + ((q >> a) & 1) - (neg ? 1 : 0);  // odd component of o
         L.y[a] = neg ? -d[a] : d[a];
-        L.S[a] = neg ? -st[a] : st[a];
+        L.s[a] = neg ? -1 : 1;
         L.sgn[a] = neg ? -1.0f : 1.0f;
         L.axis[a] = a;
     }
-    for (int c = 0; c < 4; ++c) {
-        const int t = pats[c];
-        int b = fcc_coset(q ^ t) * g.scs + common;
-        for (int a = 0; a < 3; ++a)
-            if ((t >> a) & 1) b += adj[a];
-        L.base[c] = b;
-    }
+    for (int c = 0; c < 4; ++c) L.cb[c] = fcc_coset(q ^ pats[c]) * g.es;
+    set_axis_layout(g, L);
     L.region = (L.y[0] + L.y[1] + L.y[2] > 1.0f) ? 1 : 0;
 }
 
@@ -249,14 +262,22 @@ LSP_HD void locate(const PT x[3], const VolGeom& g, Loc& L) {
 }
 
 // Byte offset of the tap with reference-frame offset o (a lattice vector)
-// and parity pattern par: the stencil origin of its parity class plus
-// floor(o/D) steps along each signed, permuted reference axis.
+// and parity pattern par: along each reference axis r the padded index is the
+// origin for the parity of o_r plus s_r * floor(o_r / D); the per-axis terms
+// of the separable layout are summed and the coset of the tap added.
 template <int KIND>
 LSP_HD int tap_offset(const Loc& L, int o0, int o1, int o2, int par) {
-    if (KIND == kTricubic)
-        return L.base[0] + o0 * L.S[0] + o1 * L.S[1] + o2 * L.S[2];
-    const int cls = (KIND == kBcc8) ? (par ? 1 : 0) : fcc_class(par);
-    return L.base[cls] + (o0 >> 1) * L.S[0] + (o1 >> 1) * L.S[1] + (o2 >> 1) * L.S[2];
+    const int o[3] = {o0, o1, o2};
+    int off = 0;
+    for (int r = 0; r < 3; ++r) {
+        int i;
+        if (KIND == kTricubic) i = L.bidx[0][r] + o[r];
+        else if (KIND == kBcc8) i = L.bidx[par ? 1 : 0][r] + L.s[r] * (o[r] >> 1);
+        else i = L.bidx[o[r] & 1][r] + L.s[r] * (o[r] >> 1);
+        off += axis_term(i, L.lb[r], L.bs[r], L.is[r]);
+    }
+    const int cls = (KIND == kTricubic) ? 0 : ((KIND == kBcc8) ? (par ? 1 : 0) : fcc_class(par));
+    return off + L.cb[cls];
 }
 
 }  // namespace lsp

@@ -46,8 +46,7 @@ __device__ __forceinline__ float src_f32(const void* p, size_t i, bool for_narro
 
 template <int SRC, int DST>
 __global__ __launch_bounds__(256) void k_pack(const void* __restrict__ src, void* __restrict__ dst,
-                                              long long n, int X, int Y, int pad, int sy, int sz,
-                                              int base) {
+                                              long long n, int X, int Y, VolGeom g, int coset) {
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         const int x = (int)(i % X);
@@ -55,36 +54,38 @@ __global__ __launch_bounds__(256) void k_pack(const void* __restrict__ src, void
         const int y = (int)(r % Y);
         const int z = (int)(r / Y);
         const float v = src_f32<SRC>(src, (size_t)i, DST != kCF32);
-        char* d = static_cast<char*>(dst) + base + (z + pad) * sz + (y + pad) * sy;
+        const int off = coset * g.es + axis_term(x + g.pad, g.lb[0], g.bs[0], g.is[0]) +
+                        axis_term(y + g.pad, g.lb[1], g.bs[1], g.is[1]) +
+                        axis_term(z + g.pad, g.lb[2], g.bs[2], g.is[2]);
+        char* d = static_cast<char*>(dst) + off;
         if (DST == kCF32) {
-            reinterpret_cast<float*>(d)[x + pad] = v;
+            *reinterpret_cast<float*>(d) = v;
         } else if (DST == kCBF16) {
-            reinterpret_cast<unsigned short*>(d)[x + pad] = f32_to_bf16(v);
+            *reinterpret_cast<unsigned short*>(d) = f32_to_bf16(v);
         } else {
-            reinterpret_cast<unsigned short*>(d)[x + pad] =
-                __builtin_bit_cast(unsigned short, (_Float16)v);
+            *reinterpret_cast<unsigned short*>(d) = __builtin_bit_cast(unsigned short, (_Float16)v);
         }
     }
 }
 
 template <int SRC>
 hipError_t pack_src(const void* src, int ctype, void* dst, long long n, int X, int Y,
-                    const VolGeom& g, int base, hipStream_t s) {
+                    const VolGeom& g, int coset, hipStream_t s) {
     long long blocks = (n + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     if (blocks < 1) blocks = 1;
     switch (ctype) {
         case kCF32:
             hipLaunchKernelGGL((k_pack<SRC, kCF32>), dim3((unsigned)blocks), dim3(256), 0, s, src,
-                               dst, n, X, Y, g.pad, g.sy, g.sz, base);
+                               dst, n, X, Y, g, coset);
             break;
         case kCBF16:
             hipLaunchKernelGGL((k_pack<SRC, kCBF16>), dim3((unsigned)blocks), dim3(256), 0, s, src,
-                               dst, n, X, Y, g.pad, g.sy, g.sz, base);
+                               dst, n, X, Y, g, coset);
             break;
         case kCF16:
             hipLaunchKernelGGL((k_pack<SRC, kCF16>), dim3((unsigned)blocks), dim3(256), 0, s, src,
-                               dst, n, X, Y, g.pad, g.sy, g.sz, base);
+                               dst, n, X, Y, g, coset);
             break;
         default:
             return hipErrorInvalidValue;
@@ -99,12 +100,11 @@ hipError_t launch_pack(const void* src, int src_dtype, int ctype, void* dst, con
     const long long n = (long long)dims[0] * dims[1] * dims[2];
     if (n == 0) return hipSuccess;
     const int X = (int)dims[0], Y = (int)dims[1];
-    const int base = coset * g.scs;
     switch (src_dtype) {
-        case 0: return pack_src<0>(src, ctype, dst, n, X, Y, g, base, stream);  // F32
-        case 1: return pack_src<1>(src, ctype, dst, n, X, Y, g, base, stream);  // F64
-        case 2: return pack_src<2>(src, ctype, dst, n, X, Y, g, base, stream);  // BF16
-        case 3: return pack_src<3>(src, ctype, dst, n, X, Y, g, base, stream);  // F16
+        case 0: return pack_src<0>(src, ctype, dst, n, X, Y, g, coset, stream);  // F32
+        case 1: return pack_src<1>(src, ctype, dst, n, X, Y, g, coset, stream);  // F64
+        case 2: return pack_src<2>(src, ctype, dst, n, X, Y, g, coset, stream);  // BF16
+        case 3: return pack_src<3>(src, ctype, dst, n, X, Y, g, coset, stream);  // F16
     }
     return hipErrorInvalidValue;
 }

@@ -3,7 +3,11 @@ dL/dx by the gradient kernel) against the FP64 CPU checker, plus
 determinism, sum rules, autograd, finite differences and a small fit.
 
 dL/dc tolerance: |dc_gpu - dc_ref|_n <= 1e-5 * sum_i |g_i| phi(x_i - n)
-+ 1e-12 (FP32 products and sums of non-negative weights)."""
++ 1e-6 * sum_{i : n in the support box of x_i} |g_i|.  The first term covers
+the FP32 products and sums of non-negative weights; the second the absolute
+error of each weight polynomial evaluated in FP32 (at most cond * 2^-24 with
+the generator's condition number cond <= 6.5, i.e. < 4e-7), which matters
+where the true weight is near zero at the edge of the support."""
 import numpy as np
 import pytest
 import torch
@@ -30,6 +34,19 @@ def _setup(name, E, n, seed, dev, outside=True):
     return vol, c, x, g
 
 
+def _support_sum(name, E, x, a):
+    """sum of a_i over the points whose support box |x_i - n|_inf < r holds site n."""
+    pos = inputs.site_positions(name, E).astype(np.float64)   # (nc, Z, Y, X, 3)
+    r = inputs.LATTICE[name]["r"]
+    out = np.zeros(pos.shape[:-1])
+    flat = pos.reshape(-1, 3)
+    acc = out.reshape(-1)
+    for i in range(x.shape[0]):
+        near = np.all(np.abs(flat - x[i]) < r, axis=1)
+        acc[near] += a[i]
+    return out
+
+
 @pytest.mark.parametrize("name", ["tricubic", "bcc8", "fcc6"])
 def test_dLdc_matches_oracle(device, name):
     print("case dLdc", name, flush=True)
@@ -42,7 +59,8 @@ def test_dLdc_matches_oracle(device, name):
     xs = x.astype(np.float64)
     ref = np.stack(oracle.backward(ORC[name], (E, E, E), xs, g.astype(np.float64)))
     scale = np.stack(oracle.backward(ORC[name], (E, E, E), xs, np.abs(g).astype(np.float64)))
-    assert np.all(np.abs(dc - ref) <= 1e-5 * scale + 1e-12), np.abs(dc - ref).max()
+    reach = _support_sum(name, E, xs, np.abs(g).astype(np.float64))
+    assert np.all(np.abs(dc - ref) <= 1e-5 * scale + 1e-6 * reach), np.abs(dc - ref).max()
     _, gref = oracle.evaluate(ORC[name], (E, E, E), list(c.astype(np.float64)), xs, grad=True)
     np.testing.assert_allclose(dx.cpu().numpy(), g[:, None] * gref, rtol=0,
                                atol=2e-5 * np.abs(g).max())

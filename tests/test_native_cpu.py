@@ -73,12 +73,17 @@ def test_unsupported_and_invalid_arguments():
 
 
 def _site_offset(tab, geo, n):
-    """Byte offset of lattice site n in the internal layout."""
+    """Byte offset of lattice site n in the internal layout (interleaved
+    cosets, bricks of 2^lb sites per axis, zero halo)."""
     D = np.array(tab["D"])
     for m, sh in enumerate(tab["shifts"]):
         if np.all((n - np.array(sh)) % D == 0):
-            idx = (n - np.array(sh)) // D + geo["pad"]
-            return m * geo["scs"] + idx[2] * geo["sz"] + idx[1] * geo["sy"] + idx[0] * geo["sx"]
+            i = [int(v) for v in (n - np.array(sh)) // D + geo["pad"]]
+            off = m * geo["es"]
+            for a in range(3):
+                lb = geo["lb"][a]
+                off += (i[a] >> lb) * geo["bs"][a] + (i[a] & ((1 << lb) - 1)) * geo["is_"][a]
+            return off
     raise AssertionError("not a lattice site")
 
 
@@ -94,14 +99,14 @@ def test_tap_offsets_hit_the_prescribed_sites_inside_the_buffer(name, storage):
     hi = np.array([D * (d - 1) + 1 for d in dims], dtype=np.float64)
     x = rng.uniform(-7, hi.max() + 7, (6000, 3))
     # points at and around the edges of the active range, and far away
-    lo_k = np.array([geo["kmin0"], geo["kmin1"], geo["kmin2"]])
-    hi_k = np.array([geo["kmax0"], geo["kmax1"], geo["kmax2"]])
+    lo_k = np.array(geo["kmin"])
+    hi_k = np.array(geo["kmax"])
     edge = np.concatenate([lo_k + rng.uniform(-1.6, 1.6, (1500, 3)),
                            hi_k + rng.uniform(-1.6, 1.6, (1500, 3))])
     x = np.concatenate([x, edge, [[1e30, 0, 0], [-1e30, 3, 3], [np.inf, 1, 1], [np.nan, 2, 2]]])
     x = x.astype(np.float32).astype(np.float64)
     offs, flags = sp.debug_tap_offsets(dims, x, storage)
-    es = geo["sx"]
+    es = geo["es"]
     assert offs.min() >= 0 and offs.max() <= geo["nbytes"] - es  # every fetch in bounds
     active = (flags & 1) == 1
     assert flags[-1] & 2 and not active[-4:].any()
