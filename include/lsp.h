@@ -195,6 +195,41 @@ lsp_status lsp_backward(const lsp_volume* vol, const void* pts, lsp_dtype pts_dt
                         const float* dL_df, float* dL_dc, float* dL_dx, void* workspace,
                         size_t ws_bytes, hipStream_t stream);
 
+/* --------------------------------------------------------------- batches */
+
+typedef struct lsp_batch_plan lsp_batch_plan;  /* opaque: bound work list + captured graph */
+
+#define LSP_BATCH_AUTOTUNE 1  /* time candidate launch shapes at creation */
+
+/*
+ * Plan the evaluation of n_vol volumes of uneven size in one persistent
+ * launch (the per-point work of lsp_eval / lsp_eval_grad, Algorithm 1, for
+ * every volume).  Per volume v (host arrays of n_vol entries):
+ *   vols[v]  volume handle (any spline and storage type; must outlive the plan
+ *            and keep its coefficients bound)
+ *   pts[v]   device, N[v]*3 FP32 points
+ *   val[v]   device, N[v] floats, or NULL if grad[v] is given
+ *   grad[v]  (grad itself may be NULL) device N[v]*3 floats for value+gradient,
+ *            or NULL for value only
+ * Pointers and sizes are bound into the plan: lsp_batch_run evaluates
+ * whatever the bound buffers hold at that time.  The work is a list of
+ * (volume, tile) items consumed by a persistent grid through an atomic work
+ * counter; with LSP_BATCH_AUTOTUNE the tile size and grid size are chosen by
+ * timing candidates on `stream` (the outputs are written while doing so).
+ * The reset of the work counter and the persistent kernel are captured in a
+ * HIP graph.  Allocates the plan's device tables; synchronizes `stream`
+ * before returning.
+ */
+lsp_status lsp_batch_plan_create(int n_vol, const lsp_volume* const* vols, const float* const* pts,
+                                 const int64_t* N, float* const* val, float* const* grad, int flags,
+                                 hipStream_t stream, lsp_batch_plan** out);
+/* Chosen tile (points per work item), grid size and number of work items. */
+lsp_status lsp_batch_plan_info(const lsp_batch_plan* plan, int* tile, int* blocks, int* n_items);
+/* Replay the captured graph on `stream`.  Plans must not run concurrently
+ * with themselves (they share one work counter). */
+lsp_status lsp_batch_run(lsp_batch_plan* plan, hipStream_t stream);
+void lsp_batch_plan_destroy(lsp_batch_plan* plan);
+
 /* ----------------------------------------------------------- diagnostics */
 
 /*

@@ -99,8 +99,8 @@ class Spline:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            N.lib().lsp_spline_destroy(h)
+        if h is not None and h.value and N is not None and N._lib is not None:
+            N._lib.lsp_spline_destroy(h)
             self._h = None
 
 
@@ -119,8 +119,8 @@ class Volume:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            N.lib().lsp_volume_destroy(h)
+        if h is not None and h.value and N is not None and N._lib is not None:
+            N._lib.lsp_volume_destroy(h)
             self._h = None
 
     @property
@@ -198,6 +198,49 @@ class Volume:
         N.check(N.lib().lsp_backward(self._h, _ptr(pts), _TORCH_DT[pts.dtype], n, _ptr(g), _ptr(dc),
                                      _ptr(dx), ctypes.c_void_p(ws_ptr), ws_len, _stream(pts.device)))
         return dc, dx
+
+class BatchPlan:
+    """Many volumes of uneven size evaluated by one persistent launch that
+    is captured in a HIP graph; run() replays it on the current stream."""
+
+    def __init__(self, vols: Sequence[Volume], pts: Sequence[torch.Tensor],
+                 want_grad: Sequence[bool] = None, autotune: bool = True):
+        n = len(vols)
+        if len(pts) != n:
+            raise ValueError("one point tensor per volume")
+        want_grad = list(want_grad) if want_grad is not None else [False] * n
+        self.vols = list(vols)
+        self.pts = [Volume._pts(p) for p in pts]
+        for p in self.pts:
+            if p.dtype != torch.float32:
+                raise ValueError("batched points must be float32")
+        dev = self.pts[0].device
+        self.val = [torch.empty(p.shape[0], dtype=torch.float32, device=dev) for p in self.pts]
+        self.grad = [torch.empty(p.shape[0], 3, dtype=torch.float32, device=dev) if g else None
+                     for p, g in zip(self.pts, want_grad)]
+        arr = lambda xs: (ctypes.c_void_p * n)(*[x if x is not None else None for x in xs])
+        h = ctypes.c_void_p()
+        N.check(N.lib().lsp_batch_plan_create(
+            n, arr([v._h.value for v in self.vols]), arr([p.data_ptr() for p in self.pts]),
+            (ctypes.c_int64 * n)(*[p.shape[0] for p in self.pts]),
+            arr([v.data_ptr() for v in self.val]),
+            arr([g.data_ptr() if g is not None else None for g in self.grad]),
+            N.LSP_BATCH_AUTOTUNE if autotune else 0, _stream(dev), ctypes.byref(h)))
+        self._h = h
+        t, b, k = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        N.check(N.lib().lsp_batch_plan_info(h, ctypes.byref(t), ctypes.byref(b), ctypes.byref(k)))
+        self.tile, self.blocks, self.n_items = t.value, b.value, k.value
+
+    def run(self):
+        N.check(N.lib().lsp_batch_run(self._h, _stream(self.pts[0].device)))
+        return self.val, self.grad
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and N is not None and N._lib is not None:
+            N._lib.lsp_batch_plan_destroy(h)
+            self._h = None
+
 
 class LatticeSplineFn(torch.autograd.Function):
     """f = sum_n c_n phi(x - n) with gradients for the points and the

@@ -8,6 +8,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -15,6 +17,7 @@
 #include "lsp.h"
 #include "lsp_launch.h"
 #include "lsp_backward.h"
+#include "lsp_batch.h"
 #include "generated/bcc8.h"
 #include "generated/fcc6.h"
 #include "generated/tricubic.h"
@@ -515,6 +518,194 @@ lsp_status lsp_backward(const lsp_volume* vol, const void* pts, lsp_dtype pts_dt
     }
     return LSP_OK;
 }
+
+// ------------------------------------------------------------ batched plans
+
+}  // extern "C"
+
+struct lsp_batch_plan {
+    int n_vol = 0;
+    int n_items = 0;
+    int tile = 0;
+    int blocks = 0;
+    int device = 0;
+    lsp::BatchVol* d_vols = nullptr;
+    lsp::BatchItem* d_items = nullptr;
+    int* d_counter = nullptr;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+std::mutex g_tune_mu;
+std::map<std::string, std::pair<int, int>> g_tune_cache;  // signature -> (tile, blocks/CU)
+
+std::vector<lsp::BatchItem> make_items(const std::vector<lsp::BatchVol>& hv, int tile) {
+    std::vector<int> order(hv.size());
+    for (size_t v = 0; v < hv.size(); ++v) order[v] = (int)v;
+    // largest volumes first: their many tiles are handed out before the tail
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return hv[a].N > hv[b].N; });
+    std::vector<lsp::BatchItem> items;
+    for (int v : order)
+        for (int s = 0; s < hv[v].N; s += tile) items.push_back({v, s, std::min(tile, hv[v].N - s)});
+    return items;
+}
+
+void destroy_plan(lsp_batch_plan* p) {
+    if (!p) return;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->cap) (void)hipStreamDestroy(p->cap);
+    if (p->d_vols) (void)hipFree(p->d_vols);
+    if (p->d_items) (void)hipFree(p->d_items);
+    if (p->d_counter) (void)hipFree(p->d_counter);
+    delete p;
+}
+
+lsp_status upload_items(lsp_batch_plan* p, const std::vector<lsp::BatchItem>& items) {
+    if (p->d_items) (void)hipFree(p->d_items);
+    p->d_items = nullptr;
+    p->n_items = (int)items.size();
+    if (items.empty()) return LSP_OK;
+    hipError_t e = hipMalloc(&p->d_items, sizeof(lsp::BatchItem) * items.size());
+    if (e != hipSuccess) return fail(LSP_E_OOM, "hipMalloc(items): %s", hipGetErrorString(e));
+    e = hipMemcpy(p->d_items, items.data(), sizeof(lsp::BatchItem) * items.size(),
+                  hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(items)");
+    return LSP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lsp_status lsp_batch_plan_create(int n_vol, const lsp_volume* const* vols, const float* const* pts,
+                                 const int64_t* N, float* const* val, float* const* grad, int flags,
+                                 hipStream_t stream, lsp_batch_plan** out) {
+    if (!out) return fail(LSP_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (n_vol < 1 || n_vol > (1 << 16)) return fail(LSP_E_SHAPE, "n_vol %d out of [1, 65536]", n_vol);
+    if (!vols || !pts || !N || !val) return fail(LSP_E_INVALID_ARG, "NULL array argument");
+    std::vector<lsp::BatchVol> hv(n_vol);
+    long long total = 0;
+    for (int v = 0; v < n_vol; ++v) {
+        const lsp_volume* vol = vols[v];
+        if (!vol) return fail(LSP_E_INVALID_ARG, "vols[%d] is NULL", v);
+        if (N[v] < 0 || N[v] >= ((int64_t)1 << 31)) return fail(LSP_E_SHAPE, "N[%d] out of range", v);
+        const bool want_grad = grad && grad[v];
+        if (N[v] > 0 && (!pts[v] || (!val[v] && !want_grad)))
+            return fail(LSP_E_INVALID_ARG, "volume %d: pts or outputs are NULL", v);
+        lsp::BatchVol& b = hv[v];
+        b.coef = vol->buf;
+        b.nbytes = (unsigned)vol->nbytes;
+        b.kind = vol->def.kind;
+        b.ctype = vol->ctype;
+        b.N = (int)N[v];
+        b.g = vol->geom;
+        b.pts = pts[v];
+        b.val = val[v];
+        b.grad = want_grad ? grad[v] : nullptr;
+        total += N[v];
+    }
+    lsp_batch_plan* p = new (std::nothrow) lsp_batch_plan;
+    if (!p) return fail(LSP_E_OOM, "host allocation failed");
+    p->n_vol = n_vol;
+    hipError_t e = hipGetDevice(&p->device);
+    int ncu = 0;
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device);
+    if (e != hipSuccess) { destroy_plan(p); return hip_fail(e, "device query"); }
+    e = hipMalloc(&p->d_vols, sizeof(lsp::BatchVol) * n_vol);
+    if (e == hipSuccess) e = hipMalloc(&p->d_counter, sizeof(int));
+    if (e != hipSuccess) { destroy_plan(p); return fail(LSP_E_OOM, "hipMalloc: %s", hipGetErrorString(e)); }
+    e = hipMemcpy(p->d_vols, hv.data(), sizeof(lsp::BatchVol) * n_vol, hipMemcpyHostToDevice);
+    if (e != hipSuccess) { destroy_plan(p); return hip_fail(e, "hipMemcpy(vols)"); }
+
+    // signature of the batch for the tuning cache: kinds, storage, modes, sizes
+    std::string sig = std::to_string(ncu) + ":";
+    for (const lsp::BatchVol& b : hv)
+        sig += std::to_string(b.kind) + "/" + std::to_string(b.ctype) + "/" + (b.grad ? "g" : "v") +
+               "/" + std::to_string(b.N) + "/" + std::to_string(b.nbytes) + ";";
+    int tile = 4096, bpc = 8;
+    bool cached = false;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(sig);
+        if (it != g_tune_cache.end()) { tile = it->second.first; bpc = it->second.second; cached = true; }
+    }
+    if ((flags & LSP_BATCH_AUTOTUNE) && !cached && total > 0) {
+        // time every candidate launch shape on the caller's stream
+        const int tiles[3] = {1024, 4096, 16384};
+        const int bpcs[3] = {2, 4, 8};
+        hipEvent_t t0, t1;
+        (void)hipEventCreate(&t0);
+        (void)hipEventCreate(&t1);
+        float best = 1e30f;
+        for (int ti = 0; ti < 3; ++ti) {
+            std::vector<lsp::BatchItem> items = make_items(hv, tiles[ti]);
+            lsp_status st = upload_items(p, items);
+            if (st) { (void)hipEventDestroy(t0); (void)hipEventDestroy(t1); destroy_plan(p); return st; }
+            for (int bi = 0; bi < 3; ++bi) {
+                const int blocks = std::max(1, std::min(ncu * bpcs[bi], p->n_items));
+                e = lsp::launch_batch(p->d_vols, p->d_items, p->n_items, p->d_counter, blocks, stream);
+                if (e == hipSuccess) e = hipEventRecord(t0, stream);
+                for (int r = 0; r < 3 && e == hipSuccess; ++r)
+                    e = lsp::launch_batch(p->d_vols, p->d_items, p->n_items, p->d_counter, blocks, stream);
+                if (e == hipSuccess) e = hipEventRecord(t1, stream);
+                if (e == hipSuccess) e = hipEventSynchronize(t1);
+                float ms = 0;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+                if (e != hipSuccess) {
+                    (void)hipEventDestroy(t0);
+                    (void)hipEventDestroy(t1);
+                    destroy_plan(p);
+                    return hip_fail(e, "autotune launch");
+                }
+                if (ms < best) { best = ms; tile = tiles[ti]; bpc = bpcs[bi]; }
+            }
+        }
+        (void)hipEventDestroy(t0);
+        (void)hipEventDestroy(t1);
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[sig] = {tile, bpc};
+    }
+    std::vector<lsp::BatchItem> items = make_items(hv, tile);
+    lsp_status st = upload_items(p, items);
+    if (st) { destroy_plan(p); return st; }
+    p->tile = tile;
+    p->blocks = std::max(1, std::min(ncu * bpc, std::max(p->n_items, 1)));
+    // capture reset + persistent kernel into a graph on a private stream
+    e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t el = lsp::launch_batch(p->d_vols, p->d_items, p->n_items, p->d_counter, p->blocks, p->cap);
+        e = hipStreamEndCapture(p->cap, &p->graph);
+        if (e == hipSuccess) e = el;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) { destroy_plan(p); return hip_fail(e, "graph capture"); }
+    *out = p;
+    return LSP_OK;
+}
+
+lsp_status lsp_batch_plan_info(const lsp_batch_plan* p, int* tile, int* blocks, int* n_items) {
+    if (!p) return fail(LSP_E_INVALID_ARG, "plan is NULL");
+    if (tile) *tile = p->tile;
+    if (blocks) *blocks = p->blocks;
+    if (n_items) *n_items = p->n_items;
+    return LSP_OK;
+}
+
+lsp_status lsp_batch_run(lsp_batch_plan* p, hipStream_t stream) {
+    if (!p || !p->exec) return fail(LSP_E_INVALID_ARG, "plan is NULL");
+    hipError_t e = hipGraphLaunch(p->exec, stream);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return LSP_OK;
+}
+
+void lsp_batch_plan_destroy(lsp_batch_plan* p) { destroy_plan(p); }
 
 // ------------------------------------------------------------ diagnostics
 

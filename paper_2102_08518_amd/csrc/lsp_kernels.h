@@ -116,18 +116,17 @@ __device__ __forceinline__ void load_point(const PT* __restrict__ pts, int i, PT
     x[2] = pts[3 * (size_t)i + 2];
 }
 
+// One query point, all of Algorithm 1:
 // MODE kValue:     out[i] = f(x_i)
 // MODE kValueGrad: out[i] = f(x_i) (if out), grad[3i..] = grad f(x_i)
 // MODE kGradX:     grad[3i..] = gin[i] * grad f(x_i)        (dL/dx)
 template <int KIND, class CT, class PT, int MODE, bool PREDICATED>
-__global__ __launch_bounds__(256) void k_eval(const PT* __restrict__ pts, int N,
-                                              const void* __restrict__ coef, unsigned nbytes,
-                                              VolGeom g, float* __restrict__ out,
-                                              float* __restrict__ grad,
-                                              const float* __restrict__ gin) {
+__device__ __forceinline__ void eval_point(const PT* __restrict__ pts, int i,
+                                           const void* __restrict__ coef, unsigned nbytes,
+                                           const VolGeom& g, float* __restrict__ out,
+                                           float* __restrict__ grad,
+                                           const float* __restrict__ gin) {
     using T = typename Tables<KIND>::T;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
     PT x[3];
     load_point(pts, i, x);
     Loc L;
@@ -150,6 +149,17 @@ __global__ __launch_bounds__(256) void k_eval(const PT* __restrict__ pts, int N,
 #pragma unroll
         for (int a = 0; a < 3; ++a) grad[3 * (size_t)i + a] = L.active ? scale * gx[a] : fill;
     }
+}
+
+template <int KIND, class CT, class PT, int MODE, bool PREDICATED>
+__global__ __launch_bounds__(256) void k_eval(const PT* __restrict__ pts, int N,
+                                              const void* __restrict__ coef, unsigned nbytes,
+                                              VolGeom g, float* __restrict__ out,
+                                              float* __restrict__ grad,
+                                              const float* __restrict__ gin) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    eval_point<KIND, CT, PT, MODE, PREDICATED>(pts, i, coef, nbytes, g, out, grad, gin);
 }
 
 }  // namespace lsp

@@ -144,31 +144,32 @@ def test_autograd_and_finite_differences(device):
 
 
 def _design_matrix(E, x):
-    """A[i, n] = phi(x_i - n) from the checker's phi over the candidate sites."""
+    """Sparse A[i, n] = phi(x_i - n) from the checker's phi over the sites in
+    each point's support box."""
+    import scipy.sparse as sps
     pos = inputs.site_positions("bcc8", E).reshape(-1, 3).astype(np.float64)
-    r = 4.0
+    r = float(inputs.LATTICE["bcc8"]["r"])
     rows, cols, pts = [], [], []
     for i in range(x.shape[0]):
         near = np.nonzero(np.all(np.abs(pos - x[i]) < r, axis=1))[0]
         rows.append(np.full(near.size, i))
         cols.append(near)
         pts.append(x[i] - pos[near])
-    rows, cols = np.concatenate(rows), np.concatenate(cols)
     vals = oracle.phi(oracle.BCC8, np.concatenate(pts))
-    A = np.zeros((x.shape[0], pos.shape[0]))
-    A[rows, cols] = vals
-    return A
+    return sps.csr_matrix((vals, (np.concatenate(rows), np.concatenate(cols))),
+                          shape=(x.shape[0], pos.shape[0]))
 
 
 def test_adam_fit_matches_fp64_fit(device):
-    """Fit BCC coefficients (2 x 8^3) to 4000 samples of a smooth field with
-    200 Adam steps; the loss curve agrees with an FP64 Adam driven by the
-    checker's phi within 1e-3 relative."""
+    """Fit BCC coefficients (2 x 16^3, zero start) to 6000 samples of a
+    smooth field with 200 Adam steps (lr 0.05, betas 0.9/0.999, eps 1e-8)
+    through LatticeSplineFn; the loss curve follows an FP64 Adam driven by
+    the checker's phi within 1e-2 relative, and the fit converges."""
     print("case adam fit", flush=True)
-    E = 8
+    E = 16
     lo, hi = inputs.interior("bcc8", E)
     field = inputs.smooth_field(4, lo, hi)
-    x = np.random.default_rng(35).uniform(lo, hi, (4000, 3)).astype(np.float32)
+    x = np.random.default_rng(35).uniform(lo, hi, (6000, 3)).astype(np.float32)
     y = field(x.astype(np.float64))
     A = _design_matrix(E, x.astype(np.float64))
     lr, b1, b2, eps = 0.05, 0.9, 0.999, 1e-8
@@ -195,7 +196,7 @@ def test_adam_fit_matches_fp64_fit(device):
         loss = ((f - yt) ** 2).mean()
         loss.backward()
         opt.step()
-        gpu_loss.append(float(loss))
+        gpu_loss.append(float(loss.detach()))
     gpu_loss, ref_loss = np.array(gpu_loss), np.array(ref_loss)
-    assert gpu_loss[-1] < 0.05 * gpu_loss[0]
-    np.testing.assert_allclose(gpu_loss, ref_loss, rtol=1e-3, atol=1e-7)
+    assert ref_loss[-1] < 1e-3 * ref_loss[0]
+    np.testing.assert_allclose(gpu_loss, ref_loss, rtol=1e-2, atol=1e-7)
