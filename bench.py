@@ -34,6 +34,35 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+def kernel_source_hash() -> str:
+    """Hash of every kernel source and generated table the library builds from."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2102_08518_amd", "csrc")
+    for dirpath, _, files in sorted(os.walk(csrc)):
+        for f in sorted(files):
+            if f.endswith((".h", ".hip")):
+                with open(os.path.join(dirpath, f), "rb") as fh:
+                    h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_path: str):
+    """HBM bytes per launch of the forward kernel from the committed counter
+    summary (profiles/traffic.json: FETCH_SIZE and WRITE_SIZE scaled by a
+    device copy of known size), or None when the kernel sources changed
+    since the counters were taken."""
+    try:
+        with open(os.path.join(ROOT, "profiles", "traffic.json")) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    entry = t.get(kernel_path)
+    if not entry or t.get("source_hash") != kernel_source_hash():
+        return None
+    return entry["bytes_per_launch"]
+
+
 def time_fn(fn, steps, warmup, stream):
     import torch
     for _ in range(warmup):
@@ -87,14 +116,28 @@ def main():
     out = torch.empty(n, dtype=torch.float32, device=dev)
     res = {}
     vols = {}
+    paths = {}
     for storage in ("f32", "bf16"):
         vol = api.Volume(sp, (E, E, E), storage)
         vol.set(ct)
         vols[storage] = vol
-        ms = time_fn(lambda: vol.eval(xt, out), args.steps, args.warmup, stream)
+        ws, _, _ = vol._binned_ws(xt, None)
+        for path in ("direct", "binned"):
+            if path == "direct":
+                fn = lambda: vol.eval(xt, out)
+            else:
+                fn = lambda: vol.eval(xt, out, binned=True, workspace=ws)
+            ms = time_fn(fn, args.steps, args.warmup, stream)
+            paths[(storage, path)] = ms
+            log("%s %s forward: %.4f ms/step, %.3e points/s" % (storage, path, ms, n / (ms * 1e-3)))
+        best = min(("direct", "binned"), key=lambda pth: paths[(storage, pth)])
+        ms = paths[(storage, best)]
+        if best == "direct":
+            vol.eval(xt, out)
+        else:
+            vol.eval(xt, out, binned=True, workspace=ws)
         f = out.double().cpu().numpy()
-        res[storage] = dict(ms=ms, pts_per_s=n / (ms * 1e-3), f=f)
-        log("%s forward: %.4f ms/step, %.3e points/s" % (storage, ms, n / (ms * 1e-3)))
+        res[storage] = dict(ms=ms, pts_per_s=n / (ms * 1e-3), f=f, path=best)
 
     # forward + backward (dL/dc, dL/dx) for an MSE loss against the field
     fb = None
@@ -104,8 +147,11 @@ def main():
         wsb = vol.workspace_bytes(n)
         ws = torch.empty(wsb + 256, dtype=torch.uint8, device=dev)
 
+        fwd_binned = res["f32"]["path"] == "binned"
+        wsf, _, _ = vol._binned_ws(xt, None)
+
         def step_fb():
-            vol.eval(xt, out)
+            vol.eval(xt, out, binned=fwd_binned, workspace=wsf)
             vol.backward(xt, g, want_dc=True, want_dx=True, workspace=ws)
 
         ms_fb = time_fn(step_fb, max(args.steps // 5, 3), 2, stream)
@@ -134,8 +180,9 @@ def main():
     achieved = flops / t_k / 1e12
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
             "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
-            "traffic": None,
-            "kernel": "k_eval<bcc8,f32,f32,value>",
+            "traffic": measured_traffic("bcc8_f32_" + res["f32"]["path"]),
+            "kernel": ("k_eval<bcc8,f32,f32,value>" if res["f32"]["path"] == "direct"
+                       else "k_eval_binned<bcc8,f32,f32,value> (+ binning kernels, whole step timed)"),
             "algorithmic_flops_per_point": 2 * fma,
             "frac_of_nonpacked_peak": round(achieved / PEAK_FP32_NONPACKED_TFLOPS, 4),
             "hbm_compulsory_GBs": round(16.0 * n / t_k / 1e9, 1),
@@ -169,8 +216,11 @@ def main():
         "config": {"workload": "BCC 2x64^3 (L rows [-1,1,1],[1,-1,1],[1,1,-1]), 8-direction box "
                                "spline, smooth field + N(0,0.01) coefficients, 2^22 uniform "
                                "interior points, forward",
-                   "points": n, "coeffs": int(c.size), "storage": "f32"},
+                   "points": n, "coeffs": int(c.size), "storage": "f32",
+                   "path": res["f32"]["path"]},
+        "paths_ms": {"%s_%s" % k: round(v, 5) for k, v in paths.items()},
         "bf16": {"value": round(res["bf16"]["pts_per_s"], 1), "ms_per_step": round(res["bf16"]["ms"], 5),
+                 "path": res["bf16"]["path"],
                  "speedup_vs_f32": round(res["f32"]["ms"] / res["bf16"]["ms"], 3),
                  "max_rel_err_vs_fp64": err["bf16"]["max_rel_vs_fp64"],
                  "max_rel_err_vs_stored": err["bf16"]["max_rel_vs_stored"]},

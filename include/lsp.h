@@ -176,6 +176,22 @@ lsp_status lsp_eval_grad(const lsp_volume* vol, const void* pts, lsp_dtype pts_d
                          float* val, float* grad, hipStream_t stream);
 
 /*
+ * The same results as lsp_eval (val) and lsp_eval_grad (grad, nullable), bit
+ * for bit, computed in spatially binned order: the points are first grouped
+ * by coarse blocks of the lattice (counted, scanned and scattered into the
+ * workspace), then evaluated block by block so that the stencils of
+ * neighbouring work-items share cache lines; results are written back to the
+ * callers' indices.  Pays off for large N in random order.  Workspace:
+ * device, at least lsp_eval_binned_workspace_size bytes, 256-byte aligned.
+ * Allocates nothing.
+ */
+lsp_status lsp_eval_binned_workspace_size(const lsp_volume* vol, lsp_dtype pts_dtype, int64_t N,
+                                          size_t* bytes);
+lsp_status lsp_eval_binned(const lsp_volume* vol, const void* pts, lsp_dtype pts_dtype, int64_t N,
+                           float* val, float* grad, void* workspace, size_t ws_bytes,
+                           hipStream_t stream);
+
+/*
  * Bytes of device workspace lsp_backward needs for N points.
  */
 lsp_status lsp_backward_workspace_size(const lsp_volume* vol, int64_t N, size_t* bytes);

@@ -8,12 +8,12 @@
 //   2. stable radix sort of (cell, point index)   -- a library sort;
 //   3. cell start offsets by lower-bound search on the sorted keys;
 //   4. per sorted point, the weights g_i w_j(y_i) of every union tap j (the
-//      per-tap polynomials of the reference sub-region), stored tap-major,
-//      and its symmetry id;
+//      per-tap polynomials of the reference sub-region), one padded row per
+//      point, and its symmetry id;
 //   5. per cell, partial sums P[u][cell] over the cell's points for every
 //      offset v_u of the symmetry-closed stencil U: a point with symmetry
 //      element G reaches the site cell + v_u through the tap j with
-//      G^T o_j = v_u (generated table J[G][u]);
+//      G^T o_j = v_u (generated table J[G][u], inverted to u(G, j));
 //   6. per stored site n, dL/dc_n = sum over u of P[u][n - v_u].
 // Every sum runs in a fixed order (sorted points, then U), so the result is
 // bit-reproducible.
@@ -92,6 +92,12 @@ __global__ __launch_bounds__(kBlk) void k_cell_offsets(const int* __restrict__ k
     }
 }
 
+// Weight row stride (floats): the union stencil rounded up to whole float4s.
+template <int KIND>
+constexpr int row_stride() {
+    return (Tables<KIND>::T::kTaps + 3) / 4 * 4;
+}
+
 template <int KIND>
 __device__ __forceinline__ void tap_weights(const Loc& L, float* w) {
     if (KIND == kTricubic) {
@@ -104,58 +110,90 @@ __device__ __forceinline__ void tap_weights(const Loc& L, float* w) {
     }
 }
 
-template <int KIND, class PT>
+// Per sorted point: its tap weights g_i w_j(y_i) (one padded row) and
+// symmetry id; with dL_dx, also dL/dx_i = g_i grad f(x_i), computed here in
+// cell order so that neighbouring work-items gather neighbouring
+// coefficients.
+template <int KIND, class CT, class PT, bool DX>
 __global__ __launch_bounds__(kBlk) void k_point_weights(const PT* __restrict__ pts,
                                                         const int* __restrict__ skeys,
                                                         const int* __restrict__ svals, int N,
                                                         int ncell, VolGeom g,
+                                                        const void* __restrict__ coef,
+                                                        unsigned nbytes,
                                                         const float* __restrict__ gin,
                                                         float* __restrict__ W,
-                                                        unsigned char* __restrict__ sym) {
+                                                        unsigned char* __restrict__ sym,
+                                                        float* __restrict__ dL_dx) {
     using T = typename Tables<KIND>::T;
     const int p = blockIdx.x * kBlk + threadIdx.x;
     if (p >= N) return;
-    if (skeys[p] >= ncell) return;  // inactive: never read by the gather
     const int i = svals[p];
+    if (DX) eval_point<KIND, CT, PT, kGradX, false>(pts, i, i, coef, nbytes, g, nullptr, dL_dx, gin);
+    if (skeys[p] >= ncell) return;  // inactive: no weights, never read by the gather
     PT x[3];
     load_point(pts, i, x);
     Loc L;
     locate<KIND>(x, g, L);
-    float w[T::kTaps];
+    constexpr int RS = row_stride<KIND>();
+    float w[RS];
     tap_weights<KIND>(L, w);
-    const float gi = gin[i];
 #pragma unroll
-    for (int j = 0; j < T::kTaps; ++j) W[(size_t)j * N + p] = gi * w[j];
+    for (int j = T::kTaps; j < RS; ++j) w[j] = 0.0f;
+    const float gi = gin[i];
+    float4* row = reinterpret_cast<float4*>(W + (size_t)p * RS);
+#pragma unroll
+    for (int q = 0; q < RS / 4; ++q)
+        row[q] = make_float4(gi * w[4 * q], gi * w[4 * q + 1], gi * w[4 * q + 2], gi * w[4 * q + 3]);
     sym[p] = (unsigned char)sym_id<KIND>(L);
 }
 
-// P[u][cell] = sum over the cell's points p (sorted order) of W[J[sym_p][u]][p].
+constexpr int kPartBlk = 128;
+
+// P[u][cell] = sum over the cell's points p (sorted order) of the weight of
+// the tap j with G_p^T o_j = v_u.  Each thread owns one cell and keeps its
+// |U| accumulators in LDS (indexed by u(G, j)); every slot has one owner, so
+// the adds happen in program order.
 template <int KIND>
-__global__ __launch_bounds__(kBlk) void k_cell_partials(const int* __restrict__ off,
-                                                        const unsigned char* __restrict__ sym,
-                                                        const float* __restrict__ W, int N,
-                                                        int ncell, float* __restrict__ P) {
+__global__ __launch_bounds__(kPartBlk) void k_cell_partials(const int* __restrict__ off,
+                                                            const unsigned char* __restrict__ sym,
+                                                            const float* __restrict__ W, int ncell,
+                                                            float* __restrict__ P) {
     using T = typename Tables<KIND>::T;
     constexpr int NU = T::kNumU;
-    __shared__ signed char J[T::kNumSym * NU];
-    for (int t = threadIdx.x; t < T::kNumSym * NU; t += kBlk) J[t] = T::kJ[t / NU][t % NU];
-    __syncthreads();
-    const int c = blockIdx.x * kBlk + threadIdx.x;
-    if (c >= ncell) return;
-    float acc[NU];
-#pragma unroll
-    for (int u = 0; u < NU; ++u) acc[u] = 0.0f;
-    const int b = off[c], e = off[c + 1];
-    for (int p = b; p < e; ++p) {
-        const signed char* row = J + (int)sym[p] * NU;
-#pragma unroll
-        for (int u = 0; u < NU; ++u) {
-            const int j = row[u];
-            if (j >= 0) acc[u] += W[(size_t)j * N + p];
-        }
+    constexpr int NT = T::kTaps;
+    constexpr int RS = row_stride<KIND>();
+    constexpr int SLOTS = NU | 1;   // odd stride between threads' slots
+    __shared__ unsigned char Uinv[T::kNumSym * NT];
+    __shared__ float acc[kPartBlk * SLOTS];
+    for (int t = threadIdx.x; t < T::kNumSym * NU; t += kPartBlk) {
+        const int sg = t / NU, u = t % NU;
+        const int j = T::kJ[sg][u];
+        if (j >= 0) Uinv[sg * NT + j] = (unsigned char)u;
     }
+    float* mine = acc + threadIdx.x * SLOTS;
+    for (int u = 0; u < NU; ++u) mine[u] = 0.0f;
+    __syncthreads();
+    const int c = blockIdx.x * kPartBlk + threadIdx.x;
+    const int b = c < ncell ? off[c] : 0, e = c < ncell ? off[c + 1] : 0;
+    for (int p = b; p < e; ++p) {
+        const int sg = sym[p];
+        const float4* row = reinterpret_cast<const float4*>(W + (size_t)p * RS);
+        float w[RS];
 #pragma unroll
-    for (int u = 0; u < NU; ++u) P[(size_t)u * ncell + c] = acc[u];
+        for (int q = 0; q < RS / 4; ++q) {
+            const float4 v = row[q];
+            w[4 * q] = v.x;
+            w[4 * q + 1] = v.y;
+            w[4 * q + 2] = v.z;
+            w[4 * q + 3] = v.w;
+        }
+        const unsigned char* ui = Uinv + sg * NT;
+#pragma unroll
+        for (int j = 0; j < NT; ++j) mine[ui[j]] += w[j];
+    }
+    if (c >= ncell) return;
+    for (int u = 0; u < NU; ++u) P[(size_t)u * ncell + c] = mine[u];
 }
 
 // dL/dc_n = sum_u P[u][n - v_u], one thread per stored site in the canonical
@@ -251,7 +289,7 @@ bool layout(int kind, int n_cosets, const int dims[3], int pad, long long N, Lay
     L->vals_out = o; o += nb;
     L->off = o; o += align256(sizeof(int) * ((size_t)cg.ncell + 1));
     L->sym = o; o += align256((size_t)n);
-    L->W = o; o += align256(sizeof(float) * (size_t)n * taps_of(kind));
+    L->W = o; o += align256(sizeof(float) * (size_t)n * ((taps_of(kind) + 3) / 4 * 4));
     L->P = o; o += align256(sizeof(float) * (size_t)cg.ncell * nu_of(kind));
     L->tmp = o; o += align256(tmp);
     L->tmp_bytes = tmp;
@@ -259,7 +297,7 @@ bool layout(int kind, int n_cosets, const int dims[3], int pad, long long N, Lay
     return true;
 }
 
-template <int KIND, class PT>
+template <int KIND, class CT, class PT>
 hipError_t run(const BackwardArgs& a, const Layout& ly) {
     using T = typename Tables<KIND>::T;
     char* ws = static_cast<char*>(a.ws);
@@ -294,15 +332,21 @@ hipError_t run(const BackwardArgs& a, const Layout& ly) {
         if (e != hipSuccess) return e;
     }
     if (N > 0) {
-        hipLaunchKernelGGL((k_point_weights<KIND, PT>), dim3(nblk), dim3(kBlk), 0, a.stream, pts,
-                           keys_out, vals_out, N, cg.ncell, a.g, a.dL_df, W, sym);
+        if (a.dL_dx)
+            hipLaunchKernelGGL((k_point_weights<KIND, CT, PT, true>), dim3(nblk), dim3(kBlk), 0,
+                               a.stream, pts, keys_out, vals_out, N, cg.ncell, a.g, a.coef, a.nbytes,
+                               a.dL_df, W, sym, a.dL_dx);
+        else
+            hipLaunchKernelGGL((k_point_weights<KIND, CT, PT, false>), dim3(nblk), dim3(kBlk), 0,
+                               a.stream, pts, keys_out, vals_out, N, cg.ncell, a.g, a.coef, a.nbytes,
+                               a.dL_df, W, sym, a.dL_dx);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     {
-        const int cblocks = (cg.ncell + kBlk - 1) / kBlk;
-        hipLaunchKernelGGL((k_cell_partials<KIND>), dim3(cblocks), dim3(kBlk), 0, a.stream, off, sym,
-                           W, N, cg.ncell, P);
+        const int cblocks = (cg.ncell + kPartBlk - 1) / kPartBlk;
+        hipLaunchKernelGGL((k_cell_partials<KIND>), dim3(cblocks), dim3(kPartBlk), 0, a.stream, off,
+                           sym, W, cg.ncell, P);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -312,6 +356,21 @@ hipError_t run(const BackwardArgs& a, const Layout& ly) {
                        a.dims[0], a.dims[1], a.dims[2], a.n_cosets, a.dL_dc);
     (void)sizeof(T);
     return hipGetLastError();
+}
+
+template <int KIND, class CT>
+hipError_t run_ct(const BackwardArgs& a, const Layout& ly) {
+    return a.pts_f64 ? run<KIND, CT, double>(a, ly) : run<KIND, CT, float>(a, ly);
+}
+
+template <int KIND>
+hipError_t run_pt(const BackwardArgs& a, const Layout& ly) {
+    switch (a.ctype) {
+        case kCF32: return run_ct<KIND, float>(a, ly);
+        case kCBF16: return run_ct<KIND, bf16_t>(a, ly);
+        case kCF16: return run_ct<KIND, f16_t>(a, ly);
+    }
+    return hipErrorInvalidValue;
 }
 
 }  // namespace
@@ -328,9 +387,9 @@ hipError_t launch_backward_coef(const BackwardArgs& a) {
     if (!layout(a.kind, a.n_cosets, a.dims, a.g.pad, a.N, &ly)) return hipErrorInvalidValue;
     if (a.ws_bytes < ly.total) return hipErrorInvalidValue;
     switch (a.kind) {
-        case kTricubic: return a.pts_f64 ? run<kTricubic, double>(a, ly) : run<kTricubic, float>(a, ly);
-        case kBcc8: return a.pts_f64 ? run<kBcc8, double>(a, ly) : run<kBcc8, float>(a, ly);
-        case kFcc6: return a.pts_f64 ? run<kFcc6, double>(a, ly) : run<kFcc6, float>(a, ly);
+        case kTricubic: return run_pt<kTricubic>(a, ly);
+        case kBcc8: return run_pt<kBcc8>(a, ly);
+        case kFcc6: return run_pt<kFcc6>(a, ly);
     }
     return hipErrorInvalidValue;
 }

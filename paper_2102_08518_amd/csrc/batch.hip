@@ -25,7 +25,7 @@ template <int KIND, class CT, int MODE>
 __device__ __forceinline__ void run_item(const BatchVol& v, int start, int count) {
     const int end = start + count;
     for (int p = start + (int)threadIdx.x; p < end; p += kBatchBlock)
-        eval_point<KIND, CT, float, MODE, false>(v.pts, p, v.coef, v.nbytes, v.g, v.val, v.grad,
+        eval_point<KIND, CT, float, MODE, false>(v.pts, p, p, v.coef, v.nbytes, v.g, v.val, v.grad,
                                                  nullptr);
 }
 

@@ -18,6 +18,7 @@
 #include "lsp_launch.h"
 #include "lsp_backward.h"
 #include "lsp_batch.h"
+#include "lsp_binned.h"
 #include "generated/bcc8.h"
 #include "generated/fcc6.h"
 #include "generated/tricubic.h"
@@ -178,6 +179,27 @@ const std::vector<SplineDef>& defs() {
 }
 
 int elem_size(int ctype) { return ctype == lsp::kCF32 ? 4 : 2; }
+
+// Dynamic LDS per evaluation workgroup, read once from LSP_EVAL_LDS (bytes):
+// a tuning knob that lowers occupancy (fewer waves share each CU's L1).
+// FCC 6-direction: evaluate both reference polynomials and select
+// (LSP_FCC_PREDICATED=1) instead of branching on the sub-region.
+bool fcc_predicated() {
+    static const bool v = [] {
+        const char* env = getenv("LSP_FCC_PREDICATED");
+        return env && env[0] == '1';
+    }();
+    return v;
+}
+
+unsigned eval_lds_bytes() {
+    static const unsigned v = [] {
+        const char* env = getenv("LSP_EVAL_LDS");
+        long x = env ? strtol(env, nullptr, 10) : 0;
+        return (unsigned)(x < 0 ? 0 : (x > 65536 ? 65536 : x));
+    }();
+    return v;
+}
 
 int ctype_of(lsp_dtype storage) {
     switch (storage) {
@@ -434,7 +456,7 @@ static lsp_status run_eval(const lsp_volume* vol, const void* pts, lsp_dtype pd,
     a.ctype = vol->ctype;
     a.pts_f64 = pd == LSP_F64;
     a.mode = mode;
-    a.predicated = false;
+    a.predicated = fcc_predicated();
     a.pts = pts;
     a.N = (int)N;
     a.coef = vol->buf;
@@ -444,6 +466,7 @@ static lsp_status run_eval(const lsp_volume* vol, const void* pts, lsp_dtype pd,
     a.grad = grad;
     a.gin = gin;
     a.stream = stream;
+    a.lds_bytes = eval_lds_bytes();
     hipError_t e = hipSuccess;
     switch (a.kind) {
         case lsp::kTricubic: e = lsp::launch_eval_tricubic(a); break;
@@ -471,6 +494,64 @@ lsp_status lsp_eval_grad(const lsp_volume* vol, const void* pts, lsp_dtype pts_d
     return run_eval(vol, pts, pts_dtype, N, lsp::kValueGrad, val, grad, nullptr, stream);
 }
 
+static lsp::BinGeom bin_geom(const lsp_volume* vol) {
+    lsp::BinGeom bg{};
+    int64_t P[3];
+    for (int a = 0; a < 3; ++a) P[a] = vol->dims[a] + 2 * vol->def.pad;
+    for (bg.lb = 2;; ++bg.lb) {
+        int64_t n = 1;
+        for (int a = 0; a < 3; ++a) {
+            bg.nb[a] = (int)((P[a] + (1 << bg.lb) - 1) >> bg.lb);
+            n *= bg.nb[a];
+        }
+        if (n <= lsp::kMaxBins) {
+            bg.nbins = (int)n;
+            break;
+        }
+    }
+    return bg;
+}
+
+lsp_status lsp_eval_binned_workspace_size(const lsp_volume* vol, lsp_dtype pts_dtype, int64_t N,
+                                          size_t* bytes) {
+    lsp_status st = check_eval_args(vol, (const void*)1, pts_dtype, N);
+    if (st) return st;
+    if (!bytes) return fail(LSP_E_INVALID_ARG, "bytes is NULL");
+    *bytes = lsp::binned_workspace_bytes(bin_geom(vol), (int)N, pts_dtype == LSP_F64);
+    return LSP_OK;
+}
+
+lsp_status lsp_eval_binned(const lsp_volume* vol, const void* pts, lsp_dtype pts_dtype, int64_t N,
+                           float* val, float* grad, void* workspace, size_t ws_bytes,
+                           hipStream_t stream) {
+    lsp_status st = check_eval_args(vol, pts, pts_dtype, N);
+    if (st) return st;
+    if (N > 0 && !val) return fail(LSP_E_INVALID_ARG, "val is NULL");
+    if (N == 0) return LSP_OK;
+    lsp::BinnedArgs a{};
+    a.bg = bin_geom(vol);
+    const size_t need = lsp::binned_workspace_bytes(a.bg, (int)N, pts_dtype == LSP_F64);
+    if (!workspace || ws_bytes < need)
+        return fail(LSP_E_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+    if (((uintptr_t)workspace & 255) != 0) return fail(LSP_E_WORKSPACE, "workspace must be 256-byte aligned");
+    a.kind = vol->def.kind;
+    a.ctype = vol->ctype;
+    a.pts_f64 = pts_dtype == LSP_F64;
+    a.pts = pts;
+    a.N = (int)N;
+    a.coef = vol->buf;
+    a.nbytes = (unsigned)vol->nbytes;
+    a.g = vol->geom;
+    a.out = val;
+    a.grad = grad;
+    a.ws = workspace;
+    a.ws_bytes = ws_bytes;
+    a.stream = stream;
+    hipError_t e = lsp::launch_binned(a);
+    if (e != hipSuccess) return hip_fail(e, "binned evaluation launch");
+    return LSP_OK;
+}
+
 lsp_status lsp_backward_workspace_size(const lsp_volume* vol, int64_t N, size_t* bytes) {
     if (!vol || !bytes) return fail(LSP_E_INVALID_ARG, "NULL argument");
     if (N < 0 || N >= ((int64_t)1 << 31)) return fail(LSP_E_SHAPE, "N = %lld out of [0, 2^31)", (long long)N);
@@ -487,7 +568,7 @@ lsp_status lsp_backward(const lsp_volume* vol, const void* pts, lsp_dtype pts_dt
     lsp_status st = check_eval_args(vol, pts, pts_dtype, N);
     if (st) return st;
     if (N > 0 && !dL_df && (dL_dc || dL_dx)) return fail(LSP_E_INVALID_ARG, "dL_df is NULL");
-    if (dL_dx && N > 0) {
+    if (dL_dx && !dL_dc && N > 0) {
         st = run_eval(vol, pts, pts_dtype, N, lsp::kGradX, nullptr, dL_dx, dL_df, stream);
         if (st) return st;
     }
@@ -508,8 +589,11 @@ lsp_status lsp_backward(const lsp_volume* vol, const void* pts, lsp_dtype pts_dt
         b.g = vol->geom;
         b.n_cosets = vol->def.n_cosets;
         for (int a = 0; a < 3; ++a) b.dims[a] = (int)vol->dims[a];
+        b.coef = vol->buf;
+        b.nbytes = (unsigned)vol->nbytes;
         b.dL_df = dL_df;
         b.dL_dc = dL_dc;
+        b.dL_dx = N > 0 ? dL_dx : nullptr;
         b.ws = workspace;
         b.ws_bytes = ws_bytes;
         b.stream = stream;

@@ -12,7 +12,7 @@ constexpr int kBlock = 256;
 template <int KIND, class CT, class PT, int MODE, bool PRED>
 hipError_t launch_one(const EvalArgs& a) {
     const int blocks = (a.N + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL((k_eval<KIND, CT, PT, MODE, PRED>), dim3(blocks), dim3(kBlock), 0, a.stream,
+    hipLaunchKernelGGL((k_eval<KIND, CT, PT, MODE, PRED>), dim3(blocks), dim3(kBlock), a.lds_bytes, a.stream,
                        static_cast<const PT*>(a.pts), a.N, a.coef, a.nbytes, a.g, a.out, a.grad,
                        a.gin);
     return hipGetLastError();

@@ -116,12 +116,13 @@ __device__ __forceinline__ void load_point(const PT* __restrict__ pts, int i, PT
     x[2] = pts[3 * (size_t)i + 2];
 }
 
-// One query point, all of Algorithm 1:
-// MODE kValue:     out[i] = f(x_i)
-// MODE kValueGrad: out[i] = f(x_i) (if out), grad[3i..] = grad f(x_i)
-// MODE kGradX:     grad[3i..] = gin[i] * grad f(x_i)        (dL/dx)
+// One query point, all of Algorithm 1 (x read at index i, results written
+// at index o):
+// MODE kValue:     out[o] = f(x_i)
+// MODE kValueGrad: out[o] = f(x_i) (if out), grad[3o..] = grad f(x_i)
+// MODE kGradX:     grad[3o..] = gin[o] * grad f(x_i)        (dL/dx)
 template <int KIND, class CT, class PT, int MODE, bool PREDICATED>
-__device__ __forceinline__ void eval_point(const PT* __restrict__ pts, int i,
+__device__ __forceinline__ void eval_point(const PT* __restrict__ pts, int i, int o,
                                            const void* __restrict__ coef, unsigned nbytes,
                                            const VolGeom& g, float* __restrict__ out,
                                            float* __restrict__ grad,
@@ -137,17 +138,17 @@ __device__ __forceinline__ void eval_point(const PT* __restrict__ pts, int i,
     const float qnan = __builtin_nanf("");
     if (MODE == kValue) {
         const float f = poly_value<KIND, PREDICATED>(c, L);
-        out[i] = L.active ? f : (L.nan ? qnan : 0.0f);
+        out[o] = L.active ? f : (L.nan ? qnan : 0.0f);
     } else {
         float gr[3], gx[3];
         const float f = poly_value_grad<KIND, PREDICATED>(c, L, gr);
         grad_to_global(L, gr, gx);
         const float fill = L.nan ? qnan : 0.0f;
         float scale = 1.0f;
-        if (MODE == kGradX) scale = gin[i];
-        if (MODE == kValueGrad && out) out[i] = L.active ? f : fill;
+        if (MODE == kGradX) scale = gin[o];
+        if (MODE == kValueGrad && out) out[o] = L.active ? f : fill;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) grad[3 * (size_t)i + a] = L.active ? scale * gx[a] : fill;
+        for (int a = 0; a < 3; ++a) grad[3 * (size_t)o + a] = L.active ? scale * gx[a] : fill;
     }
 }
 
@@ -159,7 +160,7 @@ __global__ __launch_bounds__(256) void k_eval(const PT* __restrict__ pts, int N,
                                               const float* __restrict__ gin) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
-    eval_point<KIND, CT, PT, MODE, PREDICATED>(pts, i, coef, nbytes, g, out, grad, gin);
+    eval_point<KIND, CT, PT, MODE, PREDICATED>(pts, i, i, coef, nbytes, g, out, grad, gin);
 }
 
 }  // namespace lsp

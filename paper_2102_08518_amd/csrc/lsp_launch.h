@@ -26,6 +26,7 @@ struct EvalArgs {
     float* grad;
     const float* gin;
     hipStream_t stream;
+    unsigned lds_bytes;  // dynamic LDS per workgroup (occupancy control), usually 0
 };
 
 hipError_t launch_eval_tricubic(const EvalArgs& a);
