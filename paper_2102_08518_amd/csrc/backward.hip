@@ -189,8 +189,10 @@ __global__ __launch_bounds__(kPartBlk) void k_cell_partials(const int* __restric
             w[4 * q + 3] = v.w;
         }
         const unsigned char* ui = Uinv + sg * NT;
+        // one owner per slot: the LDS add needs no read-modify-write chain and
+        // the accumulation order stays the program order of this thread
 #pragma unroll
-        for (int j = 0; j < NT; ++j) mine[ui[j]] += w[j];
+        for (int j = 0; j < NT; ++j) atomicAdd(&mine[ui[j]], w[j]);
     }
     if (c >= ncell) return;
     for (int u = 0; u < NU; ++u) P[(size_t)u * ncell + c] = mine[u];

@@ -257,12 +257,17 @@ lsp_status make_geom(const SplineDef& d, const int64_t dims[3], int ctype, lsp::
         while ((1 << l) < br[a]) ++l;
         g.lb[a] = l;
     }
-    g.is[0] = (int)site;
-    g.is[1] = (int)(br[0] * site);
-    g.is[2] = (int)(br[0] * br[1] * site);
-    g.bs[0] = (int)brick;
-    g.bs[1] = (int)(nb[0] * brick);
-    g.bs[2] = (int)(nb[0] * nb[1] * brick);
+    if (nb[0] * nb[1] >= ((i64)1 << 24))
+        return fail(LSP_E_SHAPE, "%lld x %lld bricks per slab exceed 2^24", (long long)nb[0],
+                    (long long)nb[1]);
+    auto log2i = [](i64 v) { int l = 0; while (((i64)1 << l) < v) ++l; return l; };
+    g.lis[0] = log2i(site);
+    g.lis[1] = log2i(br[0] * site);
+    g.lis[2] = log2i(br[0] * br[1] * site);
+    g.nbs[0] = 1;
+    g.nbs[1] = (int)nb[0];
+    g.nbs[2] = (int)(nb[0] * nb[1]);
+    g.lbb = log2i(brick);
     for (int a = 0; a < 3; ++a) {
         int shmax = 0;
         for (int m = 0; m < d.n_cosets; ++m) shmax = std::max(shmax, d.shift[m][a]);
@@ -494,11 +499,18 @@ lsp_status lsp_eval_grad(const lsp_volume* vol, const void* pts, lsp_dtype pts_d
     return run_eval(vol, pts, pts_dtype, N, lsp::kValueGrad, val, grad, nullptr, stream);
 }
 
+// Bin extent 2^lb coset units: the smallest lb >= LSP_BIN_LB (default 2)
+// with at most kMaxBins bins.
 static lsp::BinGeom bin_geom(const lsp_volume* vol) {
+    static const int lb0 = [] {
+        const char* env = getenv("LSP_BIN_LB");
+        const int v = env ? atoi(env) : 2;
+        return v < 1 ? 1 : (v > 8 ? 8 : v);
+    }();
     lsp::BinGeom bg{};
     int64_t P[3];
     for (int a = 0; a < 3; ++a) P[a] = vol->dims[a] + 2 * vol->def.pad;
-    for (bg.lb = 2;; ++bg.lb) {
+    for (bg.lb = lb0;; ++bg.lb) {
         int64_t n = 1;
         for (int a = 0; a < 3; ++a) {
             bg.nb[a] = (int)((P[a] + (1 << bg.lb) - 1) >> bg.lb);
@@ -841,8 +853,8 @@ lsp_status lsp_debug_geometry(const lsp_spline* sp, const int64_t dims[3], lsp_d
     lsp_status st = make_geom(sp->def, dims, ctype, &g, nbytes);
     if (st) return st;
     int v[20] = {g.es, g.pad, g.kmin[0], g.kmin[1], g.kmin[2], g.kmax[0], g.kmax[1], g.kmax[2],
-                 g.lb[0], g.lb[1], g.lb[2], g.bs[0], g.bs[1], g.bs[2], g.is[0], g.is[1], g.is[2],
-                 ctype, sp->def.n_cosets, 0};
+                 g.lb[0], g.lb[1], g.lb[2], g.nbs[0] << g.lbb, g.nbs[1] << g.lbb, g.nbs[2] << g.lbb,
+                 1 << g.lis[0], 1 << g.lis[1], 1 << g.lis[2], ctype, sp->def.n_cosets, 0};
     memcpy(out, v, sizeof(v));
     return LSP_OK;
 }

@@ -8,7 +8,7 @@
 
 namespace lsp {
 
-constexpr int kMaxBins = 4096;
+constexpr int kMaxBins = 8192;
 
 // Bins are blocks of 2^lb x 2^lb x 2^lb indices of the padded coset grid.
 struct BinGeom {

@@ -10,6 +10,10 @@
 // possible.  With i = idx + pad (non-negative), the byte offset of site idx
 // in coset m is separable per axis:
 //     m * es + sum_a f_a(i_a),   f_a(i) = (i >> lb[a]) * bs[a] + (i & (2^lb[a] - 1)) * is[a]
+// Every brick and every site are powers of two bytes, so is[a] = 2^lis[a]
+// and bs[a] = nbs[a] * 2^lbb with nbs the brick-count stride (< 2^24); the
+// kernels form sum_a (i_a >> lb[a]) * nbs[a] with 24-bit multiplies and one
+// shift.
 // where idx = floor((n - shift_m) / D).  For D = 2 lattices floor(n/2)
 // equals (n - shift_m)/2 for the coset the site belongs to.
 #pragma once
@@ -34,12 +38,38 @@ struct VolGeom {
     int pad;                // halo in coset units
     int kmin[3], kmax[3];   // ROE lattice points k with any stored tap
     int lb[3];              // log2 of the brick extent per axis
-    int bs[3];              // bytes between neighbouring bricks along each axis
-    int is[3];              // bytes between neighbouring sites inside a brick
+    int nbs[3];             // bricks between neighbouring bricks along each axis
+    int lis[3];             // log2 of the bytes between neighbouring sites in a brick
+    int lbb;                // log2 of the bytes per brick
 };
 
-LSP_HD int axis_term(int i, int lb, int bs, int is) {
-    return (i >> lb) * bs + (i & ((1 << lb) - 1)) * is;
+// 24-bit products (full-rate on the GPU); operands are below 2^24 here.
+LSP_HD int mul24u(int a, int b) {
+#ifdef __HIP_DEVICE_COMPILE__
+    return (int)__umul24((unsigned)a, (unsigned)b);
+#else
+    return a * b;
+#endif
+}
+LSP_HD int mul24s(int a, int b) {
+#ifdef __HIP_DEVICE_COMPILE__
+    return __mul24(a, b);
+#else
+    return a * b;
+#endif
+}
+
+// Brick part (in bricks) and in-brick part (in bytes) of one axis.
+LSP_HD int brick_term(int i, int lb, int nbs) { return mul24u(i >> lb, nbs); }
+LSP_HD int inner_term(int i, int lb, int lis) { return (i & ((1 << lb) - 1)) << lis; }
+
+LSP_HD int site_offset(const VolGeom& g, const int i[3], int coset) {
+    int br = 0, in = 0;
+    for (int a = 0; a < 3; ++a) {
+        br += brick_term(i[a], g.lb[a], g.nbs[a]);
+        in += inner_term(i[a], g.lb[a], g.lis[a]);
+    }
+    return (br << g.lbb) + in + coset * g.es;
 }
 
 // Result of locating one point.
@@ -48,7 +78,8 @@ struct Loc {
     int bidx[2][3];    // padded index origin per reference axis, for even / odd offsets
     int cb[4];         // coset byte offset per tap parity class
     int s[3];          // +-1: reflection of each reference axis
-    int lb[3], bs[3], is[3];  // layout of the global axis behind each reference axis
+    int lb[3], nbs[3], lis[3];  // layout of the global axis behind each reference axis
+    int lbb;           // log2 of the bytes per brick
     int axis[3];       // global axis of each reference axis
     float sgn[3];      // sign of each reference axis (reflection)
     int region;        // reference sub-region (polynomial) index
@@ -61,9 +92,10 @@ LSP_HD void set_axis_layout(const VolGeom& g, Loc& L) {
     for (int r = 0; r < 3; ++r) {
         const int a = L.axis[r];
         L.lb[r] = a == 0 ? g.lb[0] : (a == 1 ? g.lb[1] : g.lb[2]);
-        L.bs[r] = a == 0 ? g.bs[0] : (a == 1 ? g.bs[1] : g.bs[2]);
-        L.is[r] = a == 0 ? g.is[0] : (a == 1 ? g.is[1] : g.is[2]);
+        L.nbs[r] = a == 0 ? g.nbs[0] : (a == 1 ? g.nbs[1] : g.nbs[2]);
+        L.lis[r] = a == 0 ? g.lis[0] : (a == 1 ? g.lis[1] : g.lis[2]);
     }
+    L.lbb = g.lbb;
 }
 
 // Coordinates are clamped to +-2^22 before rounding so the integer
@@ -268,16 +300,17 @@ LSP_HD void locate(const PT x[3], const VolGeom& g, Loc& L) {
 template <int KIND>
 LSP_HD int tap_offset(const Loc& L, int o0, int o1, int o2, int par) {
     const int o[3] = {o0, o1, o2};
-    int off = 0;
+    int br = 0, in = 0;
     for (int r = 0; r < 3; ++r) {
         int i;
         if (KIND == kTricubic) i = L.bidx[0][r] + o[r];
-        else if (KIND == kBcc8) i = L.bidx[par ? 1 : 0][r] + L.s[r] * (o[r] >> 1);
-        else i = L.bidx[o[r] & 1][r] + L.s[r] * (o[r] >> 1);
-        off += axis_term(i, L.lb[r], L.bs[r], L.is[r]);
+        else if (KIND == kBcc8) i = L.bidx[par ? 1 : 0][r] + mul24s(L.s[r], o[r] >> 1);
+        else i = L.bidx[o[r] & 1][r] + mul24s(L.s[r], o[r] >> 1);
+        br += brick_term(i, L.lb[r], L.nbs[r]);
+        in += inner_term(i, L.lb[r], L.lis[r]);
     }
     const int cls = (KIND == kTricubic) ? 0 : ((KIND == kBcc8) ? (par ? 1 : 0) : fcc_class(par));
-    return off + L.cb[cls];
+    return (br << L.lbb) + in + L.cb[cls];
 }
 
 }  // namespace lsp

@@ -54,9 +54,8 @@ __global__ __launch_bounds__(256) void k_pack(const void* __restrict__ src, void
         const int y = (int)(r % Y);
         const int z = (int)(r / Y);
         const float v = src_f32<SRC>(src, (size_t)i, DST != kCF32);
-        const int off = coset * g.es + axis_term(x + g.pad, g.lb[0], g.bs[0], g.is[0]) +
-                        axis_term(y + g.pad, g.lb[1], g.bs[1], g.is[1]) +
-                        axis_term(z + g.pad, g.lb[2], g.bs[2], g.is[2]);
+        const int idx[3] = {x + g.pad, y + g.pad, z + g.pad};
+        const int off = site_offset(g, idx, coset);
         char* d = static_cast<char*>(dst) + off;
         if (DST == kCF32) {
             *reinterpret_cast<float*>(d) = v;
