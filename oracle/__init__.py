@@ -115,7 +115,12 @@ ZP = Spline("zp", np.eye(2), _cols((1, 0), (0, 1), (1, 1), (1, -1)), D=(1, 1), s
 TRILINEAR = Spline("trilinear", np.eye(3), _cols(*([(1, 0, 0)] * 2 + [(0, 1, 0)] * 2 + [(0, 0, 1)] * 2)),
                    D=(1, 1, 1), shifts=[(0, 0, 0)])
 
-SPLINES = {sp.name: sp for sp in (TRICUBIC, BCC8, BCC4, FCC6, ZP, TRILINEAR)}
+# Tensor-product quadratic B-spline on Z^3: each axis direction three times.
+TRIQUADRATIC = Spline("triquadratic", np.eye(3),
+                      _cols(*([(1, 0, 0)] * 3 + [(0, 1, 0)] * 3 + [(0, 0, 1)] * 3)),
+                      D=(1, 1, 1), shifts=[(0, 0, 0)])
+
+SPLINES = {sp.name: sp for sp in (TRICUBIC, BCC8, BCC4, FCC6, ZP, TRILINEAR, TRIQUADRATIC)}
 
 
 # ---------------------------------------------------------------- calls

@@ -31,7 +31,12 @@ DIRECTIONS = {
     "tricubic": np.concatenate([_E3] * 4, axis=1),
     "bcc8": np.concatenate([_DIAG.T, _DIAG.T], axis=1),
     "fcc6": _FCC_DIRS.T.copy(),
+    "trilinear": np.concatenate([_E3] * 2, axis=1),
+    "bcc4": _DIAG.T.copy(),
+    "triquadratic": np.concatenate([_E3] * 3, axis=1),
 }
+LATTICE_OF = {"tricubic": "cc", "bcc8": "bcc", "fcc6": "fcc", "trilinear": "cc", "bcc4": "bcc",
+              "triquadratic": "cc"}
 
 
 def _stream(device: Optional[torch.device] = None) -> ctypes.c_void_p:
@@ -69,6 +74,22 @@ class Spline:
     @classmethod
     def fcc6(cls):
         return cls(LATTICES["fcc"], DIRECTIONS["fcc6"])
+
+    @classmethod
+    def trilinear(cls):
+        return cls(LATTICES["cc"], DIRECTIONS["trilinear"])
+
+    @classmethod
+    def bcc4(cls):
+        return cls(LATTICES["bcc"], DIRECTIONS["bcc4"])
+
+    @classmethod
+    def triquadratic(cls):
+        return cls(LATTICES["cc"], DIRECTIONS["triquadratic"])
+
+    @classmethod
+    def named(cls, name: str):
+        return cls(LATTICES[LATTICE_OF[name]], DIRECTIONS[name])
 
     @property
     def n_cosets(self) -> int:

@@ -32,10 +32,6 @@ namespace {
 
 constexpr int kBlk = 256;
 
-template <int KIND> struct BwdTraits;
-template <> struct BwdTraits<kTricubic> { static constexpr int D = 1; };
-template <> struct BwdTraits<kBcc8> { static constexpr int D = 2; };
-template <> struct BwdTraits<kFcc6> { static constexpr int D = 2; };
 
 // Cell grid: the padded per-coset grid of the coefficient layout, one cell
 // per lattice point, cell = coset * NC + ((K_z + pad) * PY + K_y + pad) * PX + K_x + pad
@@ -46,20 +42,14 @@ struct CellGeom {
     int ncell;
 };
 
-template <int KIND>
-__host__ __device__ __forceinline__ int coset_of(int p0, int p1, int p2) {
-    if (KIND == kTricubic) return 0;
-    if (KIND == kBcc8) return p0;
-    return fcc_coset(p0 | (p1 << 1) | (p2 << 2));
-}
 
 template <int KIND>
 __device__ __forceinline__ int cell_of(const int k[3], const CellGeom& cg) {
-    constexpr int D = BwdTraits<KIND>::D;
+    constexpr int D = TablesOf<KIND>::kD;
     const int K0 = D == 1 ? k[0] : (k[0] >> 1);
     const int K1 = D == 1 ? k[1] : (k[1] >> 1);
     const int K2 = D == 1 ? k[2] : (k[2] >> 1);
-    const int m = coset_of<KIND>(k[0] & 1, k[1] & 1, k[2] & 1);
+    const int m = coset_of_parity<KIND>(k[0] & 1, k[1] & 1, k[2] & 1);
     return m * cg.NC + ((K2 + cg.pad) * cg.PY + (K1 + cg.pad)) * cg.PX + (K0 + cg.pad);
 }
 
@@ -95,19 +85,12 @@ __global__ __launch_bounds__(kBlk) void k_cell_offsets(const int* __restrict__ k
 // Weight row stride (floats): the union stencil rounded up to whole float4s.
 template <int KIND>
 constexpr int row_stride() {
-    return (Tables<KIND>::T::kTaps + 3) / 4 * 4;
+    return (TablesOf<KIND>::kTaps + 3) / 4 * 4;
 }
 
 template <int KIND>
 __device__ __forceinline__ void tap_weights(const Loc& L, float* w) {
-    if (KIND == kTricubic) {
-        gen::tricubic_weights_r0(L.y[0], L.y[1], L.y[2], w);
-    } else if (KIND == kBcc8) {
-        gen::bcc8_weights_r0(L.y[0], L.y[1], L.y[2], w);
-    } else {
-        if (L.region) gen::fcc6_weights_r1(L.y[0], L.y[1], L.y[2], w);
-        else gen::fcc6_weights_r0(L.y[0], L.y[1], L.y[2], w);
-    }
+    PolyOf<KIND>::weights(L.y[0], L.y[1], L.y[2], L.region, w);
 }
 
 // Per sorted point: its tap weights g_i w_j(y_i) (one padded row) and
@@ -125,7 +108,7 @@ __global__ __launch_bounds__(kBlk) void k_point_weights(const PT* __restrict__ p
                                                         float* __restrict__ W,
                                                         unsigned char* __restrict__ sym,
                                                         float* __restrict__ dL_dx) {
-    using T = typename Tables<KIND>::T;
+    using T = TablesOf<KIND>;
     const int p = blockIdx.x * kBlk + threadIdx.x;
     if (p >= N) return;
     const int i = svals[p];
@@ -159,7 +142,7 @@ __global__ __launch_bounds__(kPartBlk) void k_cell_partials(const int* __restric
                                                             const unsigned char* __restrict__ sym,
                                                             const float* __restrict__ W, int ncell,
                                                             float* __restrict__ P) {
-    using T = typename Tables<KIND>::T;
+    using T = TablesOf<KIND>;
     constexpr int NU = T::kNumU;
     constexpr int NT = T::kTaps;
     constexpr int RS = row_stride<KIND>();
@@ -189,10 +172,8 @@ __global__ __launch_bounds__(kPartBlk) void k_cell_partials(const int* __restric
             w[4 * q + 3] = v.w;
         }
         const unsigned char* ui = Uinv + sg * NT;
-        // one owner per slot: the LDS add needs no read-modify-write chain and
-        // the accumulation order stays the program order of this thread
 #pragma unroll
-        for (int j = 0; j < NT; ++j) atomicAdd(&mine[ui[j]], w[j]);
+        for (int j = 0; j < NT; ++j) mine[ui[j]] += w[j];
     }
     if (c >= ncell) return;
     for (int u = 0; u < NU; ++u) P[(size_t)u * ncell + c] = mine[u];
@@ -204,8 +185,8 @@ template <int KIND>
 __global__ __launch_bounds__(kBlk) void k_site_gather(const float* __restrict__ P, CellGeom cg,
                                                       int X, int Y, int Z, int n_cosets,
                                                       float* __restrict__ dL_dc) {
-    using T = typename Tables<KIND>::T;
-    constexpr int D = BwdTraits<KIND>::D;
+    using T = TablesOf<KIND>;
+    constexpr int D = TablesOf<KIND>::kD;
     const long long per = (long long)X * Y * Z;
     const long long s = (long long)blockIdx.x * kBlk + threadIdx.x;
     if (s >= per * n_cosets) return;
@@ -215,14 +196,8 @@ __global__ __launch_bounds__(kBlk) void k_site_gather(const float* __restrict__ 
     const int iy = (int)((r / X) % Y);
     const int iz = (int)(r / ((long long)X * Y));
     // lattice position of the site: D * idx + shift_m
-    int sh0 = 0, sh1 = 0, sh2 = 0;
-    if (KIND == kBcc8) { sh0 = sh1 = sh2 = m; }
-    if (KIND == kFcc6) {
-        sh0 = (m == 1 || m == 2) ? 1 : 0;
-        sh1 = (m == 1 || m == 3) ? 1 : 0;
-        sh2 = (m == 2 || m == 3) ? 1 : 0;
-    }
-    const int n0 = D * ix + sh0, n1 = D * iy + sh1, n2 = D * iz + sh2;
+    const int n0 = D * ix + T::kShift[m][0], n1 = D * iy + T::kShift[m][1],
+              n2 = D * iz + T::kShift[m][2];
     float acc = 0.0f;
 #pragma unroll 4
     for (int u = 0; u < T::kNumU; ++u) {
@@ -233,7 +208,7 @@ __global__ __launch_bounds__(kBlk) void k_site_gather(const float* __restrict__ 
         if (K0 < -cg.pad || K0 >= cg.PX - cg.pad || K1 < -cg.pad || K1 >= cg.PY - cg.pad ||
             K2 < -cg.pad || K2 >= cg.PZ - cg.pad)
             continue;
-        const int cm = coset_of<KIND>(c0 & 1, c1 & 1, c2 & 1);
+        const int cm = coset_of_parity<KIND>(c0 & 1, c1 & 1, c2 & 1);
         const int cell = cm * cg.NC + ((K2 + cg.pad) * cg.PY + (K1 + cg.pad)) * cg.PX + (K0 + cg.pad);
         acc += P[(size_t)u * cg.ncell + cell];
     }
@@ -248,15 +223,17 @@ struct Layout {
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 int taps_of(int kind) {
-    if (kind == kTricubic) return gen::tricubic_tables::kTaps;
-    if (kind == kBcc8) return gen::bcc8_tables::kTaps;
-    return gen::fcc6_tables::kTaps;
+#define LSP_TAPS(k) if (kind == k) return TablesOf<k>::kTaps;
+    LSP_FOR_EACH_KIND(LSP_TAPS)
+#undef LSP_TAPS
+    return 0;
 }
 
 int nu_of(int kind) {
-    if (kind == kTricubic) return gen::tricubic_tables::kNumU;
-    if (kind == kBcc8) return gen::bcc8_tables::kNumU;
-    return gen::fcc6_tables::kNumU;
+#define LSP_NU(k) if (kind == k) return TablesOf<k>::kNumU;
+    LSP_FOR_EACH_KIND(LSP_NU)
+#undef LSP_NU
+    return 0;
 }
 
 CellGeom cell_geom(const int dims[3], int pad, int n_cosets) {
@@ -301,7 +278,7 @@ bool layout(int kind, int n_cosets, const int dims[3], int pad, long long N, Lay
 
 template <int KIND, class CT, class PT>
 hipError_t run(const BackwardArgs& a, const Layout& ly) {
-    using T = typename Tables<KIND>::T;
+    using T = TablesOf<KIND>;
     char* ws = static_cast<char*>(a.ws);
     int* keys_in = reinterpret_cast<int*>(ws + ly.keys_in);
     int* vals_in = reinterpret_cast<int*>(ws + ly.vals_in);
@@ -388,11 +365,9 @@ hipError_t launch_backward_coef(const BackwardArgs& a) {
     Layout ly{};
     if (!layout(a.kind, a.n_cosets, a.dims, a.g.pad, a.N, &ly)) return hipErrorInvalidValue;
     if (a.ws_bytes < ly.total) return hipErrorInvalidValue;
-    switch (a.kind) {
-        case kTricubic: return run_pt<kTricubic>(a, ly);
-        case kBcc8: return run_pt<kBcc8>(a, ly);
-        case kFcc6: return run_pt<kFcc6>(a, ly);
-    }
+#define LSP_RUN(k) if (a.kind == k) return run_pt<k>(a, ly);
+    LSP_FOR_EACH_KIND(LSP_RUN)
+#undef LSP_RUN
     return hipErrorInvalidValue;
 }
 

@@ -61,9 +61,9 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch(const BatchVol* __restric
         const BatchItem w = items[it];
         const BatchVol v = vols[w.vol];
         switch (v.kind) {
-            case kTricubic: run_kind<kTricubic>(v, w.start, w.count); break;
-            case kBcc8: run_kind<kBcc8>(v, w.start, w.count); break;
-            default: run_kind<kFcc6>(v, w.start, w.count); break;
+#define LSP_CASE(k) case k: run_kind<k>(v, w.start, w.count); break;
+            LSP_FOR_EACH_KIND(LSP_CASE)
+#undef LSP_CASE
         }
     }
 }

@@ -26,15 +26,11 @@ namespace {
 constexpr int kBinBlk = 256;
 constexpr int kPtsPerThr = 16;
 
-template <int KIND> struct BinD;
-template <> struct BinD<kTricubic> { static constexpr int D = 1; };
-template <> struct BinD<kBcc8> { static constexpr int D = 2; };
-template <> struct BinD<kFcc6> { static constexpr int D = 2; };
 
 template <int KIND, class PT>
 __device__ __forceinline__ int bin_of(const PT* __restrict__ pts, int i, const VolGeom& g,
                                       const BinGeom& bg) {
-    constexpr int D = BinD<KIND>::D;
+    constexpr int D = TablesOf<KIND>::kD;
     PT x[3];
     load_point(pts, i, x);
     Loc L;
@@ -207,11 +203,10 @@ hipError_t launch_binned(const BinnedArgs& a) {
     if (a.bg.nbins > kMaxBins) return hipErrorInvalidValue;
     const Parts q = parts(a.bg, a.N);
     if (a.ws_bytes < q.total) return hipErrorInvalidValue;
-    switch (a.kind) {
-        case kTricubic: return a.pts_f64 ? run_ct<kTricubic, double>(a, q) : run_ct<kTricubic, float>(a, q);
-        case kBcc8: return a.pts_f64 ? run_ct<kBcc8, double>(a, q) : run_ct<kBcc8, float>(a, q);
-        case kFcc6: return a.pts_f64 ? run_ct<kFcc6, double>(a, q) : run_ct<kFcc6, float>(a, q);
-    }
+#define LSP_RUN(k) \
+    if (a.kind == k) return a.pts_f64 ? run_ct<k, double>(a, q) : run_ct<k, float>(a, q);
+    LSP_FOR_EACH_KIND(LSP_RUN)
+#undef LSP_RUN
     return hipErrorInvalidValue;
 }
 

@@ -2,5 +2,5 @@
 #include "lsp_dispatch.h"
 
 namespace lsp {
-hipError_t launch_eval_bcc8(const EvalArgs& a) { return launch_kind<kBcc8>(a); }
+template hipError_t launch_eval<kBcc8>(const EvalArgs& a);
 }  // namespace lsp

@@ -2,5 +2,5 @@
 #include "lsp_dispatch.h"
 
 namespace lsp {
-hipError_t launch_eval_fcc6(const EvalArgs& a) { return launch_kind<kFcc6>(a); }
+template hipError_t launch_eval<kFcc6>(const EvalArgs& a);
 }  // namespace lsp

@@ -2,5 +2,5 @@
 #include "lsp_dispatch.h"
 
 namespace lsp {
-hipError_t launch_eval_tricubic(const EvalArgs& a) { return launch_kind<kTricubic>(a); }
+template hipError_t launch_eval<kTricubic>(const EvalArgs& a);
 }  // namespace lsp

@@ -19,9 +19,7 @@
 #include "lsp_backward.h"
 #include "lsp_batch.h"
 #include "lsp_binned.h"
-#include "generated/bcc8.h"
-#include "generated/fcc6.h"
-#include "generated/tricubic.h"
+#include "generated/all.h"
 
 namespace {
 
@@ -77,6 +75,7 @@ bool same_lattice(const i64 L[3][3], const i64 R[3][3]) {
 
 struct SplineDef {
     int kind;
+    int lattice;                 // 0 Z^3, 1 BCC, 2 FCC
     const char* name;
     i64 L[3][3];                 // columns are generators
     std::vector<std::vector<int>> dirs;  // canonical directions, with repeats
@@ -95,86 +94,52 @@ std::vector<int> canon_dir(std::vector<int> d) {
     return d;
 }
 
-template <class T>
-void fill_counts(SplineDef& s) {
+// The host description of spline KIND, read from its generated tables.
+template <int K>
+SplineDef make_def() {
+    using T = lsp::TablesOf<K>;
+    SplineDef s{};
+    s.kind = K;
+    s.lattice = T::kLattice;
+    s.name = lsp::gen::SplineOf<K>::kName;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) s.L[i][j] = T::kL[i][j];
+    for (int d = 0; d < T::kNumDirs; ++d)
+        s.dirs.push_back(canon_dir({T::kXi[d][0], T::kXi[d][1], T::kXi[d][2]}));
+    s.n_cosets = T::kNumCosets;
+    s.D = T::kD;
+    for (int m = 0; m < 4; ++m)
+        for (int a = 0; a < 3; ++a) s.shift[m][a] = T::kShift[m][a];
     s.union_taps = T::kTaps;
+    s.taps = __builtin_popcountll(T::kRegionMask0);
     s.n_reference = T::kRegions;
     s.degree = T::kDegree;
     s.radius = T::kRadius;
     s.fma_eval = T::kFmaEval;
+    // per-axis range of stencil offsets in global axes: reflections and
+    // permutations make it the symmetric [-radius, radius]
     int lo = 0, hi = 0;
     for (int j = 0; j < T::kTaps; ++j)
         for (int a = 0; a < 3; ++a) {
             lo = std::min(lo, (int)T::kOff[j][a]);
             hi = std::max(hi, (int)T::kOff[j][a]);
         }
-    s.omin = lo;
-    s.omax = hi;
+    s.omin = T::kSymmetry == lsp::kSymNone ? lo : -s.radius;
+    s.omax = T::kSymmetry == lsp::kSymNone ? hi : s.radius;
+    // an active point's taps reach at most 2 * radius lattice units outside
+    // the stored range: ceil(2 radius / D) sites, plus one
+    s.pad = (2 * s.radius + s.D - 1) / s.D + 1;
+    return s;
 }
 
 const std::vector<SplineDef>& defs() {
-    static std::vector<SplineDef> v;
-    if (!v.empty()) return v;
-    {
-        SplineDef s{};
-        s.kind = lsp::kTricubic;
-        s.name = "tricubic";
-        i64 L[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
-        memcpy(s.L, L, sizeof(L));
-        for (int r = 0; r < 4; ++r)
-            for (int a = 0; a < 3; ++a) {
-                std::vector<int> d(3, 0);
-                d[a] = 1;
-                s.dirs.push_back(d);
-            }
-        s.n_cosets = 1;
-        s.D = 1;
-        s.taps = 64;
-        fill_counts<lsp::gen::tricubic_tables>(s);
-        s.pad = 4;
-        v.push_back(s);
-    }
-    {
-        SplineDef s{};
-        s.kind = lsp::kBcc8;
-        s.name = "bcc8";
-        // generators (-1,1,1), (1,-1,1), (1,1,-1) as columns
-        i64 L[3][3] = {{-1, 1, 1}, {1, -1, 1}, {1, 1, -1}};
-        memcpy(s.L, L, sizeof(L));
-        const int diag[4][3] = {{1, 1, 1}, {1, -1, -1}, {-1, 1, -1}, {-1, -1, 1}};
-        for (int r = 0; r < 2; ++r)
-            for (int i = 0; i < 4; ++i)
-                s.dirs.push_back(canon_dir({diag[i][0], diag[i][1], diag[i][2]}));
-        s.n_cosets = 2;
-        s.D = 2;
-        int sh[2][3] = {{0, 0, 0}, {1, 1, 1}};
-        memcpy(s.shift, sh, sizeof(sh));
-        s.taps = 32;
-        fill_counts<lsp::gen::bcc8_tables>(s);
-        s.omin = -s.radius;
-        s.omax = s.radius;
-        s.pad = 5;
-        v.push_back(s);
-    }
-    {
-        SplineDef s{};
-        s.kind = lsp::kFcc6;
-        s.name = "fcc6";
-        i64 L[3][3] = {{0, 1, 1}, {1, 0, 1}, {1, 1, 0}};
-        memcpy(s.L, L, sizeof(L));
-        const int dd[6][3] = {{1, 1, 0}, {1, -1, 0}, {1, 0, 1}, {1, 0, -1}, {0, 1, 1}, {0, 1, -1}};
-        for (int i = 0; i < 6; ++i) s.dirs.push_back(canon_dir({dd[i][0], dd[i][1], dd[i][2]}));
-        s.n_cosets = 4;
-        s.D = 2;
-        int sh[4][3] = {{0, 0, 0}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1}};
-        memcpy(s.shift, sh, sizeof(sh));
-        s.taps = 16;
-        fill_counts<lsp::gen::fcc6_tables>(s);
-        s.omin = -s.radius;
-        s.omax = s.radius;
-        s.pad = 3;
-        v.push_back(s);
-    }
+    static const std::vector<SplineDef> v = [] {
+        std::vector<SplineDef> out;
+#define LSP_DEF(k) out.push_back(make_def<k>());
+        LSP_FOR_EACH_KIND(LSP_DEF)
+#undef LSP_DEF
+        return out;
+    }();
     return v;
 }
 
@@ -212,16 +177,18 @@ int ctype_of(lsp_dtype storage) {
 
 lsp_status fail(lsp_status st, const char* fmt, ...);
 
-// Brick extent (x, y, z) of the interleaved layout per spline and element
-// size: the shapes that minimise the 128-byte lines a random point's stencil
-// touches (one brick = one line).  LSP_BRICK="bx,by,bz" overrides them.
-void brick_dims(int kind, int es, int b[3]) {
+// Brick extent (x, y, z) of the interleaved layout per lattice and element
+// size: one brick is one 128-byte line (cosets interleaved), in the shapes
+// that minimise the lines a random point's stencil touches.
+// LSP_BRICK="bx,by,bz" overrides them.
+void brick_dims(int lattice, int es, int b[3]) {
     static const int tab[3][2][3] = {
-        {{2, 4, 4}, {4, 4, 4}},   // tricubic: 4-byte, 2-byte coefficients
-        {{2, 2, 4}, {4, 4, 2}},   // BCC 8-direction (2 cosets per site)
-        {{2, 2, 2}, {2, 4, 2}},   // FCC 6-direction (4 cosets per site)
+        {{2, 4, 4}, {4, 4, 4}},   // Z^3 (1 coset per site): 4-byte, 2-byte coefficients
+        {{2, 2, 4}, {4, 4, 2}},   // BCC (2 cosets per site)
+        {{2, 2, 2}, {2, 4, 2}},   // FCC (4 cosets per site)
     };
-    for (int a = 0; a < 3; ++a) b[a] = tab[kind][es == 4 ? 0 : 1][a];
+    const int l = (lattice < 0 || lattice > 2) ? 0 : lattice;
+    for (int a = 0; a < 3; ++a) b[a] = tab[l][es == 4 ? 0 : 1][a];
     const char* env = getenv("LSP_BRICK");
     int v[3];
     if (env && sscanf(env, "%d,%d,%d", &v[0], &v[1], &v[2]) == 3) {
@@ -241,7 +208,7 @@ lsp_status make_geom(const SplineDef& d, const int64_t dims[3], int ctype, lsp::
             return fail(LSP_E_SHAPE, "dims[%d] = %lld out of [1, 2^20]", a, (long long)dims[a]);
     const int es = elem_size(ctype);
     int br[3];
-    brick_dims(d.kind, es, br);
+    brick_dims(d.lattice, es, br);
     const i64 site = (i64)d.n_cosets * es;
     i64 nb[3];
     for (int a = 0; a < 3; ++a) nb[a] = (dims[a] + 2 * d.pad + br[a] - 1) / br[a];
@@ -473,12 +440,12 @@ static lsp_status run_eval(const lsp_volume* vol, const void* pts, lsp_dtype pd,
     a.stream = stream;
     a.lds_bytes = eval_lds_bytes();
     hipError_t e = hipSuccess;
-    switch (a.kind) {
-        case lsp::kTricubic: e = lsp::launch_eval_tricubic(a); break;
-        case lsp::kBcc8: e = lsp::launch_eval_bcc8(a); break;
-        case lsp::kFcc6: e = lsp::launch_eval_fcc6(a); break;
-        default: return fail(LSP_E_UNSUPPORTED, "kind %d", a.kind);
-    }
+    bool found = false;
+#define LSP_RUN(k) \
+    if (a.kind == k) { e = lsp::launch_eval<k>(a); found = true; }
+    LSP_FOR_EACH_KIND(LSP_RUN)
+#undef LSP_RUN
+    if (!found) return fail(LSP_E_UNSUPPORTED, "kind %d", a.kind);
     if (e != hipSuccess) return hip_fail(e, "evaluation kernel launch");
     return LSP_OK;
 }
@@ -499,12 +466,12 @@ lsp_status lsp_eval_grad(const lsp_volume* vol, const void* pts, lsp_dtype pts_d
     return run_eval(vol, pts, pts_dtype, N, lsp::kValueGrad, val, grad, nullptr, stream);
 }
 
-// Bin extent 2^lb coset units: the smallest lb >= LSP_BIN_LB (default 2)
+// Bin extent 2^lb coset units: the smallest lb >= LSP_BIN_LB (default 3)
 // with at most kMaxBins bins.
 static lsp::BinGeom bin_geom(const lsp_volume* vol) {
     static const int lb0 = [] {
         const char* env = getenv("LSP_BIN_LB");
-        const int v = env ? atoi(env) : 2;
+        const int v = env ? atoi(env) : 3;
         return v < 1 ? 1 : (v > 8 ? 8 : v);
     }();
     lsp::BinGeom bg{};
@@ -805,6 +772,25 @@ void lsp_batch_plan_destroy(lsp_batch_plan* p) { destroy_plan(p); }
 
 // ------------------------------------------------------------ diagnostics
 
+}  // extern "C"
+
+template <int K>
+static void debug_offsets(const lsp::VolGeom& geom, const double* pts, int64_t N, int32_t* offs,
+                          int32_t* flags) {
+    using T = lsp::TablesOf<K>;
+    for (int64_t i = 0; i < N; ++i) {
+        float xf[3] = {(float)pts[3 * i], (float)pts[3 * i + 1], (float)pts[3 * i + 2]};
+        lsp::Loc L;
+        lsp::locate<K>(xf, geom, L);
+        flags[i] = (L.active ? 1 : 0) | (L.nan ? 2 : 0) | (L.region << 2);
+        for (int j = 0; j < T::kTaps; ++j)
+            offs[i * T::kTaps + j] =
+                lsp::tap_offset<K>(L, T::kOff[j][0], T::kOff[j][1], T::kOff[j][2], T::kParity[j]);
+    }
+}
+
+extern "C" {
+
 lsp_status lsp_debug_tap_offsets(const lsp_spline* sp, const int64_t dims[3], lsp_dtype storage,
                                  const double* pts, int64_t N, int32_t* offs, int32_t* flags) {
     if (!sp || !dims || (N > 0 && (!pts || !offs || !flags)))
@@ -815,32 +801,10 @@ lsp_status lsp_debug_tap_offsets(const lsp_spline* sp, const int64_t dims[3], ls
     size_t nbytes = 0;
     lsp_status st = make_geom(sp->def, dims, ctype, &geom, &nbytes);
     if (st) return st;
-    const int kind = sp->def.kind;
-    const int nt = sp->def.union_taps;
-    for (int64_t i = 0; i < N; ++i) {
-        float xf[3] = {(float)pts[3 * i], (float)pts[3 * i + 1], (float)pts[3 * i + 2]};
-        lsp::Loc L;
-        switch (kind) {
-            case lsp::kTricubic: lsp::locate<lsp::kTricubic>(xf, geom, L); break;
-            case lsp::kBcc8: lsp::locate<lsp::kBcc8>(xf, geom, L); break;
-            default: lsp::locate<lsp::kFcc6>(xf, geom, L); break;
-        }
-        flags[i] = (L.active ? 1 : 0) | (L.nan ? 2 : 0) | (L.region << 2);
-        for (int j = 0; j < nt; ++j) {
-            int32_t v;
-            if (kind == lsp::kTricubic) {
-                using T = lsp::gen::tricubic_tables;
-                v = lsp::tap_offset<lsp::kTricubic>(L, T::kOff[j][0], T::kOff[j][1], T::kOff[j][2], T::kParity[j]);
-            } else if (kind == lsp::kBcc8) {
-                using T = lsp::gen::bcc8_tables;
-                v = lsp::tap_offset<lsp::kBcc8>(L, T::kOff[j][0], T::kOff[j][1], T::kOff[j][2], T::kParity[j]);
-            } else {
-                using T = lsp::gen::fcc6_tables;
-                v = lsp::tap_offset<lsp::kFcc6>(L, T::kOff[j][0], T::kOff[j][1], T::kOff[j][2], T::kParity[j]);
-            }
-            offs[i * nt + j] = v;
-        }
-    }
+#define LSP_OFFS(k) \
+    if (sp->def.kind == k) debug_offsets<k>(geom, pts, N, offs, flags);
+    LSP_FOR_EACH_KIND(LSP_OFFS)
+#undef LSP_OFFS
     return LSP_OK;
 }
 

@@ -46,10 +46,15 @@ hipError_t launch_ct(const EvalArgs& a) {
 template <int KIND>
 hipError_t launch_kind(const EvalArgs& a) {
     if (a.N <= 0) return hipSuccess;
-    if constexpr (KIND == kFcc6) {
+    if constexpr (TablesOf<KIND>::kRegions > 1) {
         if (a.predicated) return launch_ct<KIND, true>(a);
     }
     return launch_ct<KIND, false>(a);
+}
+
+template <int KIND>
+hipError_t launch_eval(const EvalArgs& a) {
+    return launch_kind<KIND>(a);
 }
 
 }  // namespace lsp

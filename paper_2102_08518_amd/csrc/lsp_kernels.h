@@ -10,9 +10,6 @@
 
 #include "lsp_launch.h"
 #include "lsp_locate.h"
-#include "generated/bcc8.h"
-#include "generated/fcc6.h"
-#include "generated/tricubic.h"
 
 namespace lsp {
 
@@ -48,51 +45,29 @@ template <> struct Coef<f16_t> {
     }
 };
 
-template <int KIND> struct Tables;
-template <> struct Tables<kTricubic> { using T = gen::tricubic_tables; };
-template <> struct Tables<kBcc8> { using T = gen::bcc8_tables; };
-template <> struct Tables<kFcc6> { using T = gen::fcc6_tables; };
-
 // Fetch every tap of the union stencil (Algorithm 1's memory lookups through
 // the permuted stencil pi').
 template <int KIND, class CT>
 __device__ __forceinline__ void gather(const Loc& L, __amdgpu_buffer_rsrc_t r, float* c) {
-    using T = typename Tables<KIND>::T;
+    using T = TablesOf<KIND>;
 #pragma unroll
     for (int j = 0; j < T::kTaps; ++j)
         c[j] = Coef<CT>::ld(r, tap_offset<KIND>(L, T::kOff[j][0], T::kOff[j][1], T::kOff[j][2],
                                                 T::kParity[j]));
 }
 
-// Reference polynomial value (the unrolled reference sub-region loop,
-// Sec. 4.3; the FCC spline has two reference polynomials).
+// Reference polynomial value and gradient (the unrolled reference
+// sub-region loop of Sec. 4.3, generated per spline; two reference
+// sub-regions either branch or evaluate both and select).
 template <int KIND, bool PREDICATED>
 __device__ __forceinline__ float poly_value(const float* c, const Loc& L) {
-    if (KIND == kTricubic) return gen::tricubic_eval_r0(c, L.y[0], L.y[1], L.y[2]);
-    if (KIND == kBcc8) return gen::bcc8_eval_r0(c, L.y[0], L.y[1], L.y[2]);
-    if (PREDICATED) {
-        const float v0 = gen::fcc6_eval_r0(c, L.y[0], L.y[1], L.y[2]);
-        const float v1 = gen::fcc6_eval_r1(c, L.y[0], L.y[1], L.y[2]);
-        return L.region ? v1 : v0;
-    }
-    if (L.region) return gen::fcc6_eval_r1(c, L.y[0], L.y[1], L.y[2]);
-    return gen::fcc6_eval_r0(c, L.y[0], L.y[1], L.y[2]);
+    return PolyOf<KIND>::template value<PREDICATED>(c, L.y[0], L.y[1], L.y[2], L.region);
 }
 
-// Value and gradient in the reference frame.
 template <int KIND, bool PREDICATED>
 __device__ __forceinline__ float poly_value_grad(const float* c, const Loc& L, float* g) {
-    if (KIND == kTricubic) return gen::tricubic_eval_grad_r0(c, L.y[0], L.y[1], L.y[2], g[0], g[1], g[2]);
-    if (KIND == kBcc8) return gen::bcc8_eval_grad_r0(c, L.y[0], L.y[1], L.y[2], g[0], g[1], g[2]);
-    if (PREDICATED) {
-        float a[3], b[3];
-        const float v0 = gen::fcc6_eval_grad_r0(c, L.y[0], L.y[1], L.y[2], a[0], a[1], a[2]);
-        const float v1 = gen::fcc6_eval_grad_r1(c, L.y[0], L.y[1], L.y[2], b[0], b[1], b[2]);
-        for (int r = 0; r < 3; ++r) g[r] = L.region ? b[r] : a[r];
-        return L.region ? v1 : v0;
-    }
-    if (L.region) return gen::fcc6_eval_grad_r1(c, L.y[0], L.y[1], L.y[2], g[0], g[1], g[2]);
-    return gen::fcc6_eval_grad_r0(c, L.y[0], L.y[1], L.y[2], g[0], g[1], g[2]);
+    return PolyOf<KIND>::template value_grad<PREDICATED>(c, L.y[0], L.y[1], L.y[2], L.region, g[0],
+                                                          g[1], g[2]);
 }
 
 // Gradient back to global axes: y = G (x - k) with G a signed permutation,
@@ -127,7 +102,7 @@ __device__ __forceinline__ void eval_point(const PT* __restrict__ pts, int i, in
                                            const VolGeom& g, float* __restrict__ out,
                                            float* __restrict__ grad,
                                            const float* __restrict__ gin) {
-    using T = typename Tables<KIND>::T;
+    using T = TablesOf<KIND>;
     PT x[3];
     load_point(pts, i, x);
     Loc L;

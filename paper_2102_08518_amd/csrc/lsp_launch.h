@@ -29,9 +29,10 @@ struct EvalArgs {
     unsigned lds_bytes;  // dynamic LDS per workgroup (occupancy control), usually 0
 };
 
-hipError_t launch_eval_tricubic(const EvalArgs& a);
-hipError_t launch_eval_bcc8(const EvalArgs& a);
-hipError_t launch_eval_fcc6(const EvalArgs& a);
+// Defined in lsp_dispatch.h and instantiated once per spline kind in its own
+// translation unit (eval_<name>.hip).
+template <int KIND>
+hipError_t launch_eval(const EvalArgs& a);
 
 // Convert one caller coset array (C order [z][y][x], dims X,Y,Z, dtype
 // src_dtype as lsp_dtype) into the internal padded buffer.

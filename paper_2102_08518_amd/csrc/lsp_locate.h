@@ -24,13 +24,27 @@
 #include <math.h>
 #endif
 
+#include "generated/all.h"
+
 #ifndef LSP_HD
 #define LSP_HD __host__ __device__ __forceinline__
 #endif
 
 namespace lsp {
 
-enum Kind : int { kTricubic = 0, kBcc8 = 1, kFcc6 = 2 };
+// Spline kinds, in the order of the generated kind table (generated/all.h).
+enum Kind : int { kTricubic = 0, kBcc8 = 1, kFcc6 = 2, kTrilinear = 3, kBcc4 = 4, kTriquadratic = 5 };
+static_assert(gen::kNumKinds == 6, "kind table and Kind enum disagree");
+
+// Expands X(k) for every spline kind (compile-time dispatch).
+#define LSP_FOR_EACH_KIND(X) X(0) X(1) X(2) X(3) X(4) X(5)
+
+template <int KIND> using TablesOf = typename gen::SplineOf<KIND>::T;
+template <int KIND> using PolyOf = typename gen::SplineOf<KIND>::P;
+
+enum Lattice : int { kLatCC = 0, kLatBCC = 1, kLatFCC = 2 };
+enum Roe : int { kRoeFloor = 0, kRoeRound = 1, kRoeVoronoi = 2 };
+enum Sym : int { kSymNone = 0, kSymSigns = 1, kSymSignedPerm = 2 };
 
 // Geometry of one volume as the kernels see it.  Strides are in bytes.
 struct VolGeom {
@@ -139,20 +153,22 @@ LSP_HD void finish_common(const PT x[3], const PT k[3], const VolGeom& g, Loc& L
 // (axis[0] * 3 + axis[1]) * 8 + sign bits for signed permutations.
 template <int KIND>
 LSP_HD int sym_id(const Loc& L) {
-    if (KIND == kTricubic) return 0;
+    constexpr int S = TablesOf<KIND>::kSymmetry;
+    if (S == kSymNone) return 0;
     const int bits = (L.sgn[0] < 0.0f ? 1 : 0) | (L.sgn[1] < 0.0f ? 2 : 0) | (L.sgn[2] < 0.0f ? 4 : 0);
-    if (KIND == kFcc6) return bits;
+    if (S == kSymSigns) return bits;
     return (L.axis[0] * 3 + L.axis[1]) * 8 + bits;
 }
 
-// Tensor-product cubic on Z^3: parallelepiped ROE [0,1)^3 via floor, one
-// sub-region, no symmetry (Sec. 4.1.2, the floor form of rho).
-template <class PT>
-LSP_HD void locate_tricubic(const PT xin[3], const VolGeom& g, Loc& L) {
+// Z^3 with a parallelepiped ROE (Sec. 4.1.2): the unit cube [0,1)^3 via
+// floor, or the centred cube [-1/2,1/2)^3 via floor(x + 1/2); one
+// sub-region, no symmetry.
+template <class PT, bool CENTRED>
+LSP_HD void locate_cc(const PT xin[3], const VolGeom& g, Loc& L) {
     PT x[3], k[3];
     for (int a = 0; a < 3; ++a) {
         x[a] = is_nan(xin[a]) ? xin[a] : clampc(xin[a]);
-        k[a] = is_nan(x[a]) ? (PT)0 : fl_floor(x[a]);
+        k[a] = is_nan(x[a]) ? (PT)0 : fl_floor(CENTRED ? x[a] + (PT)0.5 : x[a]);
     }
     int ki[3];
     float d[3];
@@ -283,14 +299,25 @@ LSP_HD void locate_fcc(const PT xin[3], const VolGeom& g, Loc& L) {
     }
     for (int c = 0; c < 4; ++c) L.cb[c] = fcc_coset(q ^ pats[c]) * g.es;
     set_axis_layout(g, L);
-    L.region = (L.y[0] + L.y[1] + L.y[2] > 1.0f) ? 1 : 0;
+    L.region = 0;
 }
 
+// Region of evaluation, symmetry transform and reference sub-region of a
+// point for the spline KIND (the preamble of Algorithm 1 up to the table
+// lookups): two reference sub-regions are told apart by one plane test.
 template <int KIND, class PT>
 LSP_HD void locate(const PT x[3], const VolGeom& g, Loc& L) {
-    if (KIND == kTricubic) locate_tricubic(x, g, L);
-    else if (KIND == kBcc8) locate_bcc(x, g, L);
-    else locate_fcc(x, g, L);
+    using T = TablesOf<KIND>;
+    if (T::kLattice == kLatCC) {
+        if (T::kRoe == kRoeRound) locate_cc<PT, true>(x, g, L);
+        else locate_cc<PT, false>(x, g, L);
+    } else if (T::kLattice == kLatBCC) {
+        locate_bcc(x, g, L);
+    } else {
+        locate_fcc(x, g, L);
+    }
+    if (T::kRegions > 1)
+        L.region = (T::kSelN[0] * L.y[0] + T::kSelN[1] * L.y[1] + T::kSelN[2] * L.y[2] > T::kSelT) ? 1 : 0;
 }
 
 // Byte offset of the tap with reference-frame offset o (a lattice vector)
@@ -299,18 +326,28 @@ LSP_HD void locate(const PT x[3], const VolGeom& g, Loc& L) {
 // of the separable layout are summed and the coset of the tap added.
 template <int KIND>
 LSP_HD int tap_offset(const Loc& L, int o0, int o1, int o2, int par) {
+    constexpr int LAT = TablesOf<KIND>::kLattice;
     const int o[3] = {o0, o1, o2};
     int br = 0, in = 0;
     for (int r = 0; r < 3; ++r) {
         int i;
-        if (KIND == kTricubic) i = L.bidx[0][r] + o[r];
-        else if (KIND == kBcc8) i = L.bidx[par ? 1 : 0][r] + mul24s(L.s[r], o[r] >> 1);
+        if (LAT == kLatCC) i = L.bidx[0][r] + o[r];
+        else if (LAT == kLatBCC) i = L.bidx[par ? 1 : 0][r] + mul24s(L.s[r], o[r] >> 1);
         else i = L.bidx[o[r] & 1][r] + mul24s(L.s[r], o[r] >> 1);
         br += brick_term(i, L.lb[r], L.nbs[r]);
         in += inner_term(i, L.lb[r], L.lis[r]);
     }
-    const int cls = (KIND == kTricubic) ? 0 : ((KIND == kBcc8) ? (par ? 1 : 0) : fcc_class(par));
+    const int cls = (LAT == kLatCC) ? 0 : ((LAT == kLatBCC) ? (par ? 1 : 0) : fcc_class(par));
     return (br << L.lbb) + in + L.cb[cls];
+}
+
+// Coset index of a lattice site from the parities of its coordinates.
+template <int KIND>
+LSP_HD int coset_of_parity(int p0, int p1, int p2) {
+    constexpr int LAT = TablesOf<KIND>::kLattice;
+    if (LAT == kLatCC) return 0;
+    if (LAT == kLatBCC) return p0;
+    return fcc_coset(p0 | (p1 << 1) | (p2 << 2));
 }
 
 }  // namespace lsp

@@ -209,7 +209,10 @@ class SplineCode:
         fac = []
         for i in range(spec.s):
             bs1 = dv.BoxSpline(1, [(1,)] * mult[i], 1)
-            reg = R("unit", [((1,), 0), ((-1,), 1)], (F(1, 3),))
+            if spec.roe == "round":
+                reg = R("centred", [((1,), F(1, 2)), ((-1,), F(1, 2))], (F(1, 5),))
+            else:
+                reg = R("unit", [((1,), 0), ((-1,), 1)], (F(1, 3),))
             d1 = dv.derive_region(Spec1(), bs1, reg)
             fac.append(dict(zip([o[0] for o in d1.taps], d1.polys)))
         for o, p in zip(d.taps, d.polys):
@@ -240,7 +243,8 @@ class SplineCode:
                 "weights": [{",".join(map(str, e)): str(c) for e, c in q.t.items()} for q in loc],
             })
         return {
-            "name": spec.name, "s": spec.s, "L": [list(r) for r in spec.L],
+            "name": spec.name, "kind": spec.kind, "lattice": spec.lattice, "s": spec.s,
+            "L": [list(r) for r in spec.L],
             "Xi": [list(x) for x in spec.Xi], "D": list(spec.D), "shifts": [list(x) for x in spec.shifts],
             "roe": spec.roe, "symmetry": spec.symmetry,
             "selector": None if spec.selector is None else [list(spec.selector[0]), spec.selector[1]],
@@ -285,6 +289,22 @@ class SplineCode:
         L.append("namespace gen {")
         L.append("")
         L.append("struct %s_tables {" % nm)
+        L.append("  static constexpr int kKind = %d;" % spec.kind)
+        L.append("  static constexpr int kLattice = %d;    // 0 Z^3, 1 BCC, 2 FCC" % {"cc": 0, "bcc": 1, "fcc": 2}[spec.lattice])
+        L.append("  static constexpr int kRoe = %d;        // 0 floor cube, 1 centred cube, 2 Voronoi cell" % {"floor": 0, "round": 1, "voronoi": 2}[spec.roe])
+        L.append("  static constexpr int kSymmetry = %d;   // 0 none, 1 reflections, 2 signed permutations" % {"none": 0, "signs": 1, "signed_perm": 2}[spec.symmetry])
+        L.append("  static constexpr int kD = %d;          // coset scale" % spec.D[0])
+        L.append("  static constexpr int kNumCosets = %d;" % len(spec.shifts))
+        L.append("  static constexpr int kShift[4][3] = {%s};" % ", ".join(
+            "{%d, %d, %d}" % tuple(spec.shifts[m]) if m < len(spec.shifts) else "{0, 0, 0}" for m in range(4)))
+        L.append("  // lattice generators (columns) and box-spline directions (rows)")
+        L.append("  static constexpr int kL[3][3] = {%s};" % ", ".join("{%d, %d, %d}" % tuple(r) for r in spec.L))
+        L.append("  static constexpr int kNumDirs = %d;" % len(spec.Xi))
+        L.append("  static constexpr int kXi[kNumDirs][3] = {%s};" % ", ".join("{%d, %d, %d}" % tuple(x) for x in spec.Xi))
+        sel = spec.selector if spec.selector is not None else ((0, 0, 0), 0)
+        L.append("  // reference sub-region 1 where n . y > t (two reference sub-regions only)")
+        L.append("  static constexpr float kSelN[3] = {%s};" % ", ".join(flit(v) for v in sel[0]))
+        L.append("  static constexpr float kSelT = %s;" % flit(sel[1]))
         L.append("  static constexpr int kTaps = %d;       // union stencil size" % len(self.union))
         L.append("  static constexpr int kRegions = %d;    // reference sub-regions" % len(self.regions))
         L.append("  static constexpr int kRadius = %d;     // max |offset component|" % max(abs(v) for o in self.union for v in o))
@@ -317,6 +337,7 @@ class SplineCode:
         else:
             for k in range(len(self.regions)):
                 L += self._emit_region(k)
+        L += self._emit_poly_struct()
         L.append("}  // namespace gen")
         L.append("}  // namespace lsp")
         L.append("")
@@ -457,6 +478,68 @@ class SplineCode:
         return L
 
 
+def _emit_poly_struct_impl(nm: str, nreg: int) -> List[str]:
+    """Uniform entry points over the reference sub-regions: the unrolled
+    reference sub-region loop of Sec. 4.3, branchy or predicated."""
+    L = ["// uniform entry points: the reference sub-region loop (Sec. 4.3)",
+         "struct %s_poly {" % nm,
+         "  template <bool PRED>",
+         "  static __device__ __forceinline__ float value(const float* __restrict__ c, float y0, float y1, float y2, int region) {"]
+    if nreg == 1:
+        L += ["    (void)region;", "    return %s_eval_r0(c, y0, y1, y2);" % nm, "  }"]
+    else:
+        L += ["    if (PRED) {",
+              "      const float v0 = %s_eval_r0(c, y0, y1, y2);" % nm,
+              "      const float v1 = %s_eval_r1(c, y0, y1, y2);" % nm,
+              "      return region ? v1 : v0;",
+              "    }",
+              "    if (region) return %s_eval_r1(c, y0, y1, y2);" % nm,
+              "    return %s_eval_r0(c, y0, y1, y2);" % nm, "  }"]
+    L += ["  template <bool PRED>",
+          "  static __device__ __forceinline__ float value_grad(const float* __restrict__ c, float y0, float y1, float y2, int region,",
+          "                                                    float& g0, float& g1, float& g2) {"]
+    if nreg == 1:
+        L += ["    (void)region;", "    return %s_eval_grad_r0(c, y0, y1, y2, g0, g1, g2);" % nm, "  }"]
+    else:
+        L += ["    if (PRED) {",
+              "      float a0, a1, a2, b0, b1, b2;",
+              "      const float v0 = %s_eval_grad_r0(c, y0, y1, y2, a0, a1, a2);" % nm,
+              "      const float v1 = %s_eval_grad_r1(c, y0, y1, y2, b0, b1, b2);" % nm,
+              "      g0 = region ? b0 : a0; g1 = region ? b1 : a1; g2 = region ? b2 : a2;",
+              "      return region ? v1 : v0;",
+              "    }",
+              "    if (region) return %s_eval_grad_r1(c, y0, y1, y2, g0, g1, g2);" % nm,
+              "    return %s_eval_grad_r0(c, y0, y1, y2, g0, g1, g2);" % nm, "  }"]
+    L += ["  static __device__ __forceinline__ void weights(float y0, float y1, float y2, int region, float* __restrict__ w) {"]
+    if nreg == 1:
+        L += ["    (void)region;", "    %s_weights_r0(y0, y1, y2, w);" % nm, "  }"]
+    else:
+        L += ["    if (region) %s_weights_r1(y0, y1, y2, w);" % nm,
+              "    else %s_weights_r0(y0, y1, y2, w);" % nm, "  }"]
+    L += ["};", ""]
+    return L
+
+
+SplineCode._emit_poly_struct = lambda self: _emit_poly_struct_impl(self.spec.name, len(self.regions))
+
+
+def emit_kind_map(names) -> str:
+    L = ["// Generated by paper_2102_08518_amd.gen.emit: the spline kinds the library",
+         "// was generated for, indexed by kind.  Do not edit.",
+         "#pragma once", ""]
+    for nm in names:
+        L.append('#include "%s.h"' % nm)
+    L += ["", "namespace lsp {", "namespace gen {", "",
+          "constexpr int kNumKinds = %d;" % len(names), "",
+          "template <int KIND> struct SplineOf;"]
+    for nm in names:
+        sp = SPECS[nm]
+        L.append("template <> struct SplineOf<%d> { using T = %s_tables; using P = %s_poly; "
+                 "static constexpr const char* kName = \"%s\"; };" % (sp.kind, nm, nm, nm))
+    L += ["", "}  // namespace gen", "}  // namespace lsp", ""]
+    return "\n".join(L)
+
+
 def generate(names=None, out_dir=OUT_DIR, verbose=True):
     os.makedirs(out_dir, exist_ok=True)
     names = names or list(SPECS)
@@ -472,7 +555,10 @@ def generate(names=None, out_dir=OUT_DIR, verbose=True):
             json.dump(tab, fh, indent=1, sort_keys=True)
         result[nm] = tab
         if verbose:
-            print("%-9s taps %3d regions %d fma %s frames %s cond %s" % (
+            print("%-12s taps %3d regions %d fma %s frames %s cond %s" % (
                 nm, len(sc.union), len(sc.regions), tab["fma"],
                 [[str(x) for x in f] for f in sc.frames], ["%.2f" % c for c in sc.cond]))
+    if sorted(names) == sorted(SPECS):
+        with open(os.path.join(out_dir, "all.h"), "w") as fh:
+            fh.write(emit_kind_map(list(SPECS)))
     return result

@@ -30,13 +30,15 @@ def locate(tab: dict, x: np.ndarray):
     N = x.shape[0]
     if tab["roe"] == "floor":
         K = np.floor(x)
-    elif tab["name"] == "bcc8":
+    elif tab["roe"] == "round":
+        K = np.floor(x + 0.5)
+    elif tab["lattice"] == "bcc":
         k0 = 2 * np.round(x / 2)
         k1 = 2 * np.round((x - 1) / 2) + 1
         d0 = ((x - k0) ** 2).sum(1)
         d1 = ((x - k1) ** 2).sum(1)
         K = np.where((d1 < d0)[:, None], k1, k0)
-    elif tab["name"] == "fcc6":
+    elif tab["lattice"] == "fcc":
         r = np.round(x)
         odd = (r.sum(1) % 2) != 0
         res = x - r

@@ -33,12 +33,14 @@ class Spec:
     Xi: Sequence[Tuple[int, ...]]
     D: Tuple[int, ...]
     shifts: List[Tuple[int, ...]]
-    roe: str                # "floor" or "voronoi"
+    roe: str                # "floor", "round" (cube [-1/2,1/2)^s) or "voronoi"
     symmetry: str           # "none", "signs", "signed_perm"
     regions: List[Region] = field(default_factory=list)
     # region selector for several reference sub-regions: (normal, threshold):
     # region 0 if normal . y <= threshold, else region 1
     selector: Tuple = None
+    kind: int = -1          # index of the spline in the library's kind table
+    lattice: str = "cc"     # "cc", "bcc" or "fcc"
 
     def in_lattice(self, n) -> bool:
         return any(all((n[i] - sh[i]) % self.D[i] == 0 for i in range(self.s)) for sh in self.shifts)
@@ -59,7 +61,7 @@ DIAG = [(1, 1, 1), (1, -1, -1), (-1, 1, -1), (-1, -1, 1)]
 # Tensor-product cubic B-spline on Z^3 (Xi = [I I I I]); floor parallelepiped
 # ROE [0,1)^3 is a single sub-region with no symmetry needed.
 TRICUBIC = Spec(
-    name="tricubic", s=3, L=[[1, 0, 0], [0, 1, 0], [0, 0, 1]], Xi=E * 4,
+    name="tricubic", kind=0, lattice="cc", s=3, L=[[1, 0, 0], [0, 1, 0], [0, 0, 1]], Xi=E * 4,
     D=(1, 1, 1), shifts=[(0, 0, 0)], roe="floor", symmetry="none",
     regions=[Region("unit_cube",
                     [((1, 0, 0), 0), ((0, 1, 0), 0), ((0, 0, 1), 0),
@@ -72,7 +74,7 @@ TRICUBIC = Spec(
 # y = sort_desc(|x - k|) lands in the wedge 0 <= y2 <= y1 <= y0, which no knot
 # plane (y_i +- y_j in 2Z) crosses: one reference sub-region.
 BCC8 = Spec(
-    name="bcc8", s=3, L=[[-1, 1, 1], [1, -1, 1], [1, 1, -1]], Xi=DIAG * 2,
+    name="bcc8", kind=1, lattice="bcc", s=3, L=[[-1, 1, 1], [1, -1, 1], [1, 1, -1]], Xi=DIAG * 2,
     D=(2, 2, 2), shifts=[(0, 0, 0), (1, 1, 1)], roe="voronoi", symmetry="signed_perm",
     regions=[Region("wedge",
                     [((1, -1, 0), 0), ((0, 1, -1), 0), ((0, 0, 1), 0),
@@ -85,7 +87,7 @@ BCC8 = Spec(
 # positive octant, which the knot plane y0 + y1 + y2 = 1 cuts into two
 # reference sub-regions (inner tetrahedron and outer piece).
 FCC6 = Spec(
-    name="fcc6", s=3, L=[[0, 1, 1], [1, 0, 1], [1, 1, 0]],
+    name="fcc6", kind=2, lattice="fcc", s=3, L=[[0, 1, 1], [1, 0, 1], [1, 1, 0]],
     Xi=[(1, 1, 0), (1, -1, 0), (1, 0, 1), (1, 0, -1), (0, 1, 1), (0, 1, -1)],
     D=(2, 2, 2), shifts=[(0, 0, 0), (1, 1, 0), (1, 0, 1), (0, 1, 1)],
     roe="voronoi", symmetry="signs",
@@ -98,4 +100,34 @@ FCC6 = Spec(
                     (F(1, 2), F(7, 20), F(1, 4)))],
     selector=((1, 1, 1), 1))
 
-SPECS = {sp.name: sp for sp in (TRICUBIC, BCC8, FCC6)}
+_UNIT_CUBE = [((1, 0, 0), 0), ((0, 1, 0), 0), ((0, 0, 1), 0),
+              ((-1, 0, 0), 1), ((0, -1, 0), 1), ((0, 0, -1), 1)]
+_HALF = F(1, 2)
+_CENTRED_CUBE = [((1, 0, 0), _HALF), ((0, 1, 0), _HALF), ((0, 0, 1), _HALF),
+                 ((-1, 0, 0), _HALF), ((0, -1, 0), _HALF), ((0, 0, -1), _HALF)]
+
+# Order-2 splines of the paper's first comparison (Sec. 5.1): the trilinear
+# B-spline on Z^3 and the linear rhombic-dodecahedron box spline on BCC (the
+# four diagonals once; four lookups per point).  The tensor-product
+# quadratic on Z^3 (order 3) needs the centred cube as ROE, since its knot
+# planes sit at half-integers.
+TRILINEAR = Spec(
+    name="trilinear", kind=3, lattice="cc", s=3, L=[[1, 0, 0], [0, 1, 0], [0, 0, 1]], Xi=E * 2,
+    D=(1, 1, 1), shifts=[(0, 0, 0)], roe="floor", symmetry="none",
+    regions=[Region("unit_cube", _UNIT_CUBE, (F(1, 2), F(1, 3), F(1, 5)))])
+
+BCC4 = Spec(
+    name="bcc4", kind=4, lattice="bcc", s=3, L=[[-1, 1, 1], [1, -1, 1], [1, 1, -1]], Xi=DIAG,
+    D=(2, 2, 2), shifts=[(0, 0, 0), (1, 1, 1)], roe="voronoi", symmetry="signed_perm",
+    regions=[Region("wedge",
+                    [((1, -1, 0), 0), ((0, 1, -1), 0), ((0, 0, 1), 0),
+                     ((-1, 0, 0), 1), ((-1, -1, -1), F(3, 2))],
+                    (F(1, 2), F(3, 10), F(1, 10)))])
+
+TRIQUADRATIC = Spec(
+    name="triquadratic", kind=5, lattice="cc", s=3, L=[[1, 0, 0], [0, 1, 0], [0, 0, 1]], Xi=E * 3,
+    D=(1, 1, 1), shifts=[(0, 0, 0)], roe="round", symmetry="none",
+    regions=[Region("centred_cube", _CENTRED_CUBE, (F(1, 5), F(1, 7), F(1, 11)))])
+
+SPECS = {sp.name: sp for sp in sorted((TRICUBIC, BCC8, FCC6, TRILINEAR, BCC4, TRIQUADRATIC),
+                                      key=lambda sp: sp.kind)}

@@ -37,6 +37,9 @@ LATTICE = {
     "tricubic": dict(D=1, shifts=[(0, 0, 0)], r=2),
     "bcc8": dict(D=2, shifts=[(0, 0, 0), (1, 1, 1)], r=4),
     "fcc6": dict(D=2, shifts=[(0, 0, 0), (1, 1, 0), (1, 0, 1), (0, 1, 1)], r=2),
+    "trilinear": dict(D=1, shifts=[(0, 0, 0)], r=1),
+    "bcc4": dict(D=2, shifts=[(0, 0, 0), (1, 1, 1)], r=2),
+    "triquadratic": dict(D=1, shifts=[(0, 0, 0)], r=1.5),
 }
 
 

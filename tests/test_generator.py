@@ -16,7 +16,10 @@ from paper_2102_08518_amd.gen.specs import SPECS, Region, Spec
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 rng = np.random.default_rng(77)
-ORACLE_SPLINE = {"tricubic": oracle.TRICUBIC, "bcc8": oracle.BCC8, "fcc6": oracle.FCC6}
+ORACLE_SPLINE = {"tricubic": oracle.TRICUBIC, "bcc8": oracle.BCC8, "fcc6": oracle.FCC6,
+                 "trilinear": oracle.TRILINEAR, "bcc4": oracle.BCC4,
+                 "triquadratic": oracle.TRIQUADRATIC}
+ALL = list(ORACLE_SPLINE)
 
 
 def test_generator_reproduces_fig1_zp_polynomial_exactly():
@@ -38,7 +41,9 @@ def test_generator_reproduces_fig1_zp_polynomial_exactly():
         assert p.t == expect, (o, p)
 
 
-@pytest.mark.parametrize("name,taps,regions", [("tricubic", 64, 1), ("bcc8", 32, 1), ("fcc6", 16, 2)])
+@pytest.mark.parametrize("name,taps,regions", [("tricubic", 64, 1), ("bcc8", 32, 1), ("fcc6", 16, 2),
+                                               ("trilinear", 8, 1), ("bcc4", 4, 1),
+                                               ("triquadratic", 27, 1)])
 def test_stencil_sizes(name, taps, regions):
     """Tricubic: 64 fetches (Sec. 5.1); the FCC cubic spline has two reference
     sub-regions (Sec. 5.1); every stencil has vol(supp)/|det L| sites."""
@@ -48,7 +53,7 @@ def test_stencil_sizes(name, taps, regions):
         assert len(reg["taps"]) == taps
 
 
-@pytest.mark.parametrize("name", ["tricubic", "bcc8", "fcc6"])
+@pytest.mark.parametrize("name", ALL)
 def test_weights_sum_to_one_exactly(name):
     tab = interp.load_tables(name)
     for reg in tab["regions"]:
@@ -60,7 +65,7 @@ def test_weights_sum_to_one_exactly(name):
         assert tot == {"0,0,0": Fraction(1)}
 
 
-@pytest.mark.parametrize("name", ["tricubic", "bcc8", "fcc6"])
+@pytest.mark.parametrize("name", ALL)
 def test_interpreter_matches_oracle(name):
     sp = ORACLE_SPLINE[name]
     tab = interp.load_tables(name)
@@ -99,7 +104,7 @@ def test_committed_headers_are_current(tmp_path):
                 assert a.read() == b.read(), nm + ext
 
 
-@pytest.mark.parametrize("name", ["tricubic", "bcc8", "fcc6"])
+@pytest.mark.parametrize("name", ALL)
 def test_transposed_stencil_tables(name):
     """Every tap j of a located point reaches the site K + G^T o_j, and the
     transposed table maps (G, K + G^T o_j - K) back to exactly that j."""

@@ -17,7 +17,9 @@ from paper_2102_08518_amd import api, inputs
 
 pytestmark = pytest.mark.gpu
 
-ORC = {"tricubic": oracle.TRICUBIC, "bcc8": oracle.BCC8, "fcc6": oracle.FCC6}
+ORC = {"tricubic": oracle.TRICUBIC, "bcc8": oracle.BCC8, "fcc6": oracle.FCC6,
+       "trilinear": oracle.TRILINEAR, "bcc4": oracle.BCC4, "triquadratic": oracle.TRIQUADRATIC}
+ALL = list(ORC)
 
 
 def _setup(name, E, n, seed, dev, outside=True):
@@ -29,7 +31,7 @@ def _setup(name, E, n, seed, dev, outside=True):
     x = (rng.uniform(-3, hi + 3, (n, 3)) if outside
          else rng.uniform(*inputs.interior(name, E), (n, 3))).astype(np.float32)
     g = rng.normal(size=n).astype(np.float32)
-    vol = api.Volume(getattr(api.Spline, name)(), (E, E, E), "f32")
+    vol = api.Volume(api.Spline.named(name), (E, E, E), "f32")
     vol.set(torch.tensor(c, device=dev))
     return vol, c, x, g
 
@@ -47,7 +49,7 @@ def _support_sum(name, E, x, a):
     return out
 
 
-@pytest.mark.parametrize("name", ["tricubic", "bcc8", "fcc6"])
+@pytest.mark.parametrize("name", ALL)
 def test_dLdc_matches_oracle(device, name):
     print("case dLdc", name, flush=True)
     E = 9

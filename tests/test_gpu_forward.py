@@ -17,7 +17,9 @@ from paper_2102_08518_amd import api, inputs
 
 pytestmark = pytest.mark.gpu
 
-ORC = {"tricubic": oracle.TRICUBIC, "bcc8": oracle.BCC8, "fcc6": oracle.FCC6}
+ORC = {"tricubic": oracle.TRICUBIC, "bcc8": oracle.BCC8, "fcc6": oracle.FCC6,
+       "trilinear": oracle.TRILINEAR, "bcc4": oracle.BCC4, "triquadratic": oracle.TRIQUADRATIC}
+ALL = list(ORC)
 TORCH_DT = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}
 U_Q = {"f32": 2.0 ** -24, "bf16": 2.0 ** -9, "f16": 2.0 ** -11}
 
@@ -28,7 +30,7 @@ def _stored(c, storage):
 
 
 def _mk(name, E, c, storage, dev, src=torch.float32):
-    sp = getattr(api.Spline, name)()
+    sp = api.Spline.named(name)
     vol = api.Volume(sp, (E, E, E), storage)
     vol.set(torch.tensor(c, dtype=src, device=dev))
     return vol
@@ -41,7 +43,7 @@ def _points(name, E, n, rng, outside=True):
     return x.astype(np.float32)
 
 
-@pytest.mark.parametrize("name", ["tricubic", "bcc8", "fcc6"])
+@pytest.mark.parametrize("name", ALL)
 @pytest.mark.parametrize("storage", ["f32", "bf16", "f16"])
 def test_forward_matches_oracle(device, name, storage):
     print("case forward", name, storage, flush=True)
@@ -61,7 +63,7 @@ def test_forward_matches_oracle(device, name, storage):
         assert np.abs(f - ref64).max() <= U_Q[storage] * np.abs(c).max() + 2e-6
 
 
-@pytest.mark.parametrize("name", ["tricubic", "bcc8", "fcc6"])
+@pytest.mark.parametrize("name", ALL)
 def test_f64_points_and_f64_source(device, name):
     """FP64 points (x - k formed in FP64, then rounded) and an FP64 source
     array converted to FP32 storage inside the library."""
@@ -78,7 +80,7 @@ def test_f64_points_and_f64_source(device, name):
     assert np.abs(f - ref).max() <= 2e-6
 
 
-@pytest.mark.parametrize("name", ["tricubic", "bcc8", "fcc6"])
+@pytest.mark.parametrize("name", ALL)
 def test_value_and_gradient_match_oracle(device, name):
     print("case grad", name, flush=True)
     rng = np.random.default_rng(21)
@@ -100,7 +102,7 @@ def test_value_and_gradient_match_oracle(device, name):
                                atol=2e-5 * float(g.abs().max()))
 
 
-@pytest.mark.parametrize("name", ["tricubic", "bcc8", "fcc6"])
+@pytest.mark.parametrize("name", ALL)
 def test_edge_inputs(device, name):
     """Empty input, NaN (-> NaN), infinities and far points (-> 0), exact
     lattice sites and sub-region boundaries."""
@@ -169,7 +171,7 @@ def test_full_size_workloads_sampled(device, wl):
     assert np.isfinite(f).all()
 
 
-@pytest.mark.parametrize("name", ["tricubic", "bcc8", "fcc6"])
+@pytest.mark.parametrize("name", ALL)
 @pytest.mark.parametrize("storage", ["f32", "bf16"])
 def test_binned_path_is_bit_identical(device, name, storage):
     """The binned evaluation (points grouped by lattice blocks, results

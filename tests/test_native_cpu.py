@@ -31,13 +31,14 @@ def test_library_exports_every_declared_symbol():
 
 
 @pytest.mark.parametrize("name,kind,cosets,taps,union", [
-    ("tricubic", 0, 1, 64, 64), ("bcc8", 1, 2, 32, 32), ("fcc6", 2, 4, 16, 19)])
+    ("tricubic", 0, 1, 64, 64), ("bcc8", 1, 2, 32, 32), ("fcc6", 2, 4, 16, 19),
+    ("trilinear", 3, 1, 8, 8), ("bcc4", 4, 2, 4, 4), ("triquadratic", 5, 1, 27, 27)])
 def test_spline_recognition(name, kind, cosets, taps, union):
     sp = getattr(api.Spline, name)()
     assert sp.info.kind == kind and sp.info.n_cosets == cosets
     assert sp.info.taps == taps and sp.info.union_taps == union
     # another basis of the same lattice, directions shuffled and negated
-    L = api.LATTICES[{"tricubic": "cc", "bcc8": "bcc", "fcc6": "fcc"}[name]]
+    L = api.LATTICES[api.LATTICE_OF[name]]
     U = np.array([[1, 1, 0], [0, 1, 0], [0, 0, 1]], dtype=np.int32)  # unimodular
     Xi = api.DIRECTIONS[name].copy()
     rng = np.random.default_rng(3)
@@ -51,7 +52,7 @@ def test_unsupported_and_invalid_arguments():
         api.Spline(np.eye(3) * 2, api.DIRECTIONS["tricubic"])   # 2Z^3 is another lattice
     assert e.value.status == 2
     with pytest.raises(N.LspError) as e:
-        api.Spline(api.LATTICES["bcc"], api.DIRECTIONS["bcc8"][:, :4])  # 4-direction: not generated
+        api.Spline(api.LATTICES["fcc"], api.DIRECTIONS["bcc4"])  # no code for this pair
     assert e.value.status == 2
     with pytest.raises(N.LspError) as e:
         api.Spline(np.zeros((3, 3)), api.DIRECTIONS["tricubic"])
@@ -87,10 +88,10 @@ def _site_offset(tab, geo, n):
     raise AssertionError("not a lattice site")
 
 
-@pytest.mark.parametrize("name", ["tricubic", "bcc8", "fcc6"])
+@pytest.mark.parametrize("name", ["tricubic", "bcc8", "fcc6", "trilinear", "bcc4", "triquadratic"])
 @pytest.mark.parametrize("storage", ["f32", "bf16"])
 def test_tap_offsets_hit_the_prescribed_sites_inside_the_buffer(name, storage):
-    sp = getattr(api.Spline, name)()
+    sp = api.Spline.named(name)
     tab = interp.load_tables(name)
     rng = np.random.default_rng(11)
     dims = (7, 5, 6)

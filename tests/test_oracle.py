@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import oracle
-from oracle import BCC4, BCC8, FCC6, TRICUBIC, TRILINEAR, ZP
+from oracle import BCC4, BCC8, FCC6, TRICUBIC, TRILINEAR, TRIQUADRATIC, ZP
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 rng = np.random.default_rng(20210208)
@@ -25,6 +25,12 @@ def beta3(t):
 
 def hat(t):
     return np.maximum(0.0, 1 - np.abs(t))
+
+
+def beta2(t):
+    """Centred quadratic B-spline, textbook closed form."""
+    a = np.abs(t)
+    return np.where(a <= 0.5, 0.75 - a ** 2, np.where(a <= 1.5, 0.5 * (1.5 - a) ** 2, 0.0))
 
 
 # ------------------------------------------------------------ closed forms
@@ -48,6 +54,16 @@ def test_trilinear_is_tensor_product_of_hats():
     y = rng.uniform(-1.2, 1.2, (400, 3))
     ref = hat(y[:, 0]) * hat(y[:, 1]) * hat(y[:, 2])
     np.testing.assert_allclose(oracle.phi(TRILINEAR, y), ref, atol=1e-14)
+
+
+def test_triquadratic_is_tensor_product_of_quadratic_bsplines():
+    y = rng.uniform(-1.7, 1.7, (400, 3))
+    ref = beta2(y[:, 0]) * beta2(y[:, 1]) * beta2(y[:, 2])
+    np.testing.assert_allclose(oracle.phi(TRIQUADRATIC, y), ref, rtol=0, atol=1e-14)
+    # knot values 3/4, 1/2, 1/8, 0 at 0, 1/2, 1, 3/2
+    for t, v in {0: 0.75, 0.5: 0.5, 1: 0.125, 1.5: 0.0}.items():
+        got = oracle.phi(TRIQUADRATIC, [[t, 0, 0], [0, -t, 0]])
+        np.testing.assert_allclose(got, v * 0.75 ** 2, atol=1e-15)
 
 
 def test_tricubic_gradient_closed_form():
@@ -125,7 +141,7 @@ def _support_count(sp, x, radius):
 
 
 @pytest.mark.parametrize("sp,count", [(BCC4, 4), (ZP, 7), (TRICUBIC, 64), (TRILINEAR, 8),
-                                      (BCC8, 32), (FCC6, 16)])
+                                      (BCC8, 32), (FCC6, 16), (TRIQUADRATIC, 27)])
 def test_taps_at_generic_points(sp, count):
     """BCC linear: four lookups (Sec. 5.1); ZP: seven sites c0..c6 (Fig. 1);
     tricubic: 64 fetches (Sec. 5.1); in general vol(supp)/|det L|."""
@@ -161,7 +177,7 @@ def _interior(sp, E, n):
     return rng.uniform(hw + 1, hi - hw - 1, (n, sp.s))
 
 
-@pytest.mark.parametrize("sp", SPL3 + [ZP, BCC4])
+@pytest.mark.parametrize("sp", SPL3 + [ZP, BCC4, TRILINEAR, TRIQUADRATIC])
 def test_partition_of_unity_and_linear_reproduction(sp):
     E = 12 if sp.D.max() == 1 else 8
     dims = _lattice_box(sp, E)
@@ -178,7 +194,8 @@ def test_partition_of_unity_and_linear_reproduction(sp):
 
 
 @pytest.mark.parametrize("sp,M", [(TRICUBIC, np.eye(3) / 3), (BCC8, 2 * np.eye(3) / 3),
-                                  (FCC6, np.eye(3) / 3), (ZP, np.eye(2) / 4)])
+                                  (FCC6, np.eye(3) / 3), (ZP, np.eye(2) / 4),
+                                  (TRIQUADRATIC, np.eye(3) / 4)])
 def test_second_moment_is_XiXiT_over_12(sp, M):
     """Sum_n (n-x)(n-x)^T phi(x-n) = Xi Xi^T / 12 for approximation order >= 3."""
     np.testing.assert_allclose(sp.Xi @ sp.Xi.T / 12.0, M)
