@@ -18,7 +18,7 @@ STATUS = {0: "LSP_OK", 1: "LSP_E_INVALID_ARG", 2: "LSP_E_UNSUPPORTED", 3: "LSP_E
           4: "LSP_E_SHAPE", 5: "LSP_E_WORKSPACE", 6: "LSP_E_HIP", 7: "LSP_E_OOM"}
 
 # Every symbol include/lsp.h declares.
-EXPORTS = ("lsp_status_string", "lsp_last_error", "lsp_version", "lsp_spline_create",
+EXPORTS = ("lsp_status_string", "lsp_last_error", "lsp_version", "lsp_set_option", "lsp_spline_create",
            "lsp_spline_destroy", "lsp_spline_get_info", "lsp_volume_create", "lsp_volume_destroy",
            "lsp_volume_info", "lsp_volume_set_coeffs", "lsp_eval", "lsp_eval_grad",
            "lsp_eval_binned_workspace_size", "lsp_eval_binned",
@@ -27,6 +27,7 @@ EXPORTS = ("lsp_status_string", "lsp_last_error", "lsp_version", "lsp_spline_cre
            "lsp_debug_tap_offsets", "lsp_debug_geometry")
 
 LSP_BATCH_AUTOTUNE = 1
+LSP_OPT_MFMA = 1
 
 
 class LspError(RuntimeError):
@@ -65,6 +66,7 @@ def lib():
             "lsp_status_string": (ctypes.c_char_p, [ctypes.c_int]),
             "lsp_last_error": (ctypes.c_char_p, []),
             "lsp_version": (ctypes.c_char_p, []),
+            "lsp_set_option": (ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
             "lsp_spline_create": (ctypes.c_int, [ctypes.c_int, i32p, i32p, ctypes.c_int,
                                                  ctypes.POINTER(vp)]),
             "lsp_spline_destroy": (None, [vp]),

@@ -39,6 +39,18 @@ LATTICE_OF = {"tricubic": "cc", "bcc8": "bcc", "fcc6": "fcc", "trilinear": "cc",
               "triquadratic": "cc"}
 
 
+def set_option(option: int, value: int) -> None:
+    """lsp_set_option: process-wide evaluation options (N.LSP_OPT_MFMA)."""
+    N.check(N.lib().lsp_set_option(option, value))
+
+
+def use_mfma(on) -> None:
+    """How the monomial coefficients of the splines with a matrix-core form
+    are evaluated: True (matrix cores), False (per-lane FMAs) or "auto"
+    (matrix cores for 16-bit coefficient storage, the default)."""
+    set_option(N.LSP_OPT_MFMA, 2 if on == "auto" else (1 if on else 0))
+
+
 def _stream(device: Optional[torch.device] = None) -> ctypes.c_void_p:
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 

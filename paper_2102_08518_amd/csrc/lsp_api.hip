@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <new>
@@ -157,6 +158,23 @@ bool fcc_predicated() {
     return v;
 }
 
+// Matrix-core evaluation for splines that have it: LSP_OPT_MFMA (0 never,
+// 1 always, 2 for 16-bit coefficient storage), default from LSP_MFMA, else 2.
+std::atomic<int> g_opt_mfma{-1};
+
+bool mfma_for(int ctype) {
+    int o = g_opt_mfma.load(std::memory_order_relaxed);
+    if (o < 0) {
+        static const int v = [] {
+            const char* env = getenv("LSP_MFMA");
+            const int x = env ? atoi(env) : 2;
+            return x < 0 || x > 2 ? 2 : x;
+        }();
+        o = v;
+    }
+    return o == 1 || (o == 2 && ctype != lsp::kCF32);
+}
+
 unsigned eval_lds_bytes() {
     static const unsigned v = [] {
         const char* env = getenv("LSP_EVAL_LDS");
@@ -281,6 +299,15 @@ const char* lsp_status_string(lsp_status st) {
 }
 
 const char* lsp_last_error(void) { return g_err.c_str(); }
+
+lsp_status lsp_set_option(int option, int value) {
+    if (option == LSP_OPT_MFMA) {
+        if (value < 0 || value > 2) return fail(LSP_E_INVALID_ARG, "LSP_OPT_MFMA takes 0, 1 or 2");
+        g_opt_mfma.store(value, std::memory_order_relaxed);
+        return LSP_OK;
+    }
+    return fail(LSP_E_INVALID_ARG, "unknown option %d", option);
+}
 
 const char* lsp_version(void) { return "lsp 0.1 (gfx950)"; }
 
@@ -439,6 +466,7 @@ static lsp_status run_eval(const lsp_volume* vol, const void* pts, lsp_dtype pd,
     a.gin = gin;
     a.stream = stream;
     a.lds_bytes = eval_lds_bytes();
+    a.mfma = mfma_for(vol->ctype);
     hipError_t e = hipSuccess;
     bool found = false;
 #define LSP_RUN(k) \
@@ -526,6 +554,7 @@ lsp_status lsp_eval_binned(const lsp_volume* vol, const void* pts, lsp_dtype pts
     a.ws = workspace;
     a.ws_bytes = ws_bytes;
     a.stream = stream;
+    a.mfma = mfma_for(vol->ctype);
     hipError_t e = lsp::launch_binned(a);
     if (e != hipSuccess) return hip_fail(e, "binned evaluation launch");
     return LSP_OK;

@@ -4,13 +4,31 @@
 
 #include "lsp_kernels.h"
 #include "lsp_launch.h"
+#include "lsp_mfma.h"
 
 namespace lsp {
 
 constexpr int kBlock = 256;
 
+// Points per thread of the matrix-core kernel: enough blocks to fill the chip
+// several times over, the weight operands reused across the rest.
+inline int mfma_points_per_thread(int N) {
+    const int per = N / (kBlock * 2048);
+    return per < 1 ? 1 : (per > 8 ? 8 : per);
+}
+
 template <int KIND, class CT, class PT, int MODE, bool PRED>
 hipError_t launch_one(const EvalArgs& a) {
+    if constexpr (mfma_eligible<KIND>() && MODE != kGradX && !PRED) {
+        if (a.mfma) {
+            const int ppt = mfma_points_per_thread(a.N);
+            const int blocks = (a.N + kBlock * ppt - 1) / (kBlock * ppt);
+            hipLaunchKernelGGL((k_eval_mfma<KIND, CT, PT, MODE>), dim3(blocks), dim3(kBlock), 0,
+                               a.stream, static_cast<const PT*>(a.pts), a.N, ppt, a.coef, a.nbytes,
+                               a.g, a.out, a.grad);
+            return hipGetLastError();
+        }
+    }
     const int blocks = (a.N + kBlock - 1) / kBlock;
     hipLaunchKernelGGL((k_eval<KIND, CT, PT, MODE, PRED>), dim3(blocks), dim3(kBlock), a.lds_bytes, a.stream,
                        static_cast<const PT*>(a.pts), a.N, a.coef, a.nbytes, a.g, a.out, a.grad,

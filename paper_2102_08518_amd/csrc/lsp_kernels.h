@@ -96,15 +96,14 @@ __device__ __forceinline__ void load_point(const PT* __restrict__ pts, int i, PT
 // MODE kValue:     out[o] = f(x_i)
 // MODE kValueGrad: out[o] = f(x_i) (if out), grad[3o..] = grad f(x_i)
 // MODE kGradX:     grad[3o..] = gin[o] * grad f(x_i)        (dL/dx)
+// Evaluates the point x (coordinates already loaded) and writes its results
+// to output index o.
 template <int KIND, class CT, class PT, int MODE, bool PREDICATED>
-__device__ __forceinline__ void eval_point(const PT* __restrict__ pts, int i, int o,
-                                           const void* __restrict__ coef, unsigned nbytes,
-                                           const VolGeom& g, float* __restrict__ out,
-                                           float* __restrict__ grad,
-                                           const float* __restrict__ gin) {
+__device__ __forceinline__ void eval_at(const PT x[3], int o, const void* __restrict__ coef,
+                                        unsigned nbytes, const VolGeom& g,
+                                        float* __restrict__ out, float* __restrict__ grad,
+                                        const float* __restrict__ gin) {
     using T = TablesOf<KIND>;
-    PT x[3];
-    load_point(pts, i, x);
     Loc L;
     locate<KIND>(x, g, L);
     const __amdgpu_buffer_rsrc_t r = make_rsrc(coef, nbytes);
@@ -125,6 +124,17 @@ __device__ __forceinline__ void eval_point(const PT* __restrict__ pts, int i, in
 #pragma unroll
         for (int a = 0; a < 3; ++a) grad[3 * (size_t)o + a] = L.active ? scale * gx[a] : fill;
     }
+}
+
+template <int KIND, class CT, class PT, int MODE, bool PREDICATED>
+__device__ __forceinline__ void eval_point(const PT* __restrict__ pts, int i, int o,
+                                           const void* __restrict__ coef, unsigned nbytes,
+                                           const VolGeom& g, float* __restrict__ out,
+                                           float* __restrict__ grad,
+                                           const float* __restrict__ gin) {
+    PT x[3];
+    load_point(pts, i, x);
+    eval_at<KIND, CT, PT, MODE, PREDICATED>(x, o, coef, nbytes, g, out, grad, gin);
 }
 
 template <int KIND, class CT, class PT, int MODE, bool PREDICATED>

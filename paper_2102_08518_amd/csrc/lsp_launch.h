@@ -27,6 +27,7 @@ struct EvalArgs {
     const float* gin;
     hipStream_t stream;
     unsigned lds_bytes;  // dynamic LDS per workgroup (occupancy control), usually 0
+    bool mfma;           // matrix-core path where the spline has one (kValue, kValueGrad)
 };
 
 // Defined in lsp_dispatch.h and instantiated once per spline kind in its own

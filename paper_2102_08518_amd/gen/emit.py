@@ -253,7 +253,16 @@ class SplineCode:
             "tensor": self.tensor is not None,
             "regions": regs,
             "transposed": dict(zip(("U", "J"), transposed_stencil(self.union, spec.symmetry))),
+            "mfma": self._mfma_json(),
         }
+
+    def _mfma_json(self):
+        form = self.mfma_form()
+        if form is None:
+            return None
+        _, _, mons, _ = self._region_terms(0)
+        return {"Q": form["Q"], "rows": form["rows"], "Wq": form["Wq"],
+                "monomials": [list(e) for e in mons]}
 
     # -- counts
     def fma_counts(self) -> dict:
@@ -338,20 +347,102 @@ class SplineCode:
             for k in range(len(self.regions)):
                 L += self._emit_region(k)
         L += self._emit_poly_struct()
+        L += self._emit_mfma()
         L.append("}  // namespace gen")
         L.append("}  // namespace lsp")
         L.append("")
         return "\n".join(L)
 
+    def _region_terms(self, k: int):
+        """Local tap polynomials of sub-region k, their union-tap indices, and the
+        monomials in the order of the coefficient array A."""
+        d = self.regions[k]
+        loc = [p.translate(self.frames[k]) for p in d.polys]
+        uidx = [self.union.index(o) for o in d.taps]
+        mons = sorted(set().union(*[set(q.t) for q in loc]), key=lambda e: (-sum(e), e))
+        return loc, uidx, mons, {e: i for i, e in enumerate(mons)}
+
+    def mfma_form(self):
+        """Integer form of the weight matrix for the matrix-core path.
+
+        With one reference sub-region the monomial coefficients are A = W c,
+        W (monomials x union taps) constant.  Q is the least common denominator
+        of W; Wq = Q W is an integer matrix.  The form applies when Wq fits a
+        64 x 32 tile and every entry is exact in bfloat16 (at most 8 significant
+        bits), so the matrix cores form every product W_mj c_j without rounding.
+        Returns None otherwise."""
+        if self.tensor is not None or len(self.regions) != 1 or len(self.union) > 32:
+            return None
+        loc, uidx, mons, midx = self._region_terms(0)
+        if len(mons) > 64:
+            return None
+        Q = 1
+        for q in loc:
+            for c in q.t.values():
+                Q = Q * c.denominator // np.gcd(Q, c.denominator)
+        Wq = [[0] * 32 for _ in range(64)]
+        for j, q in enumerate(loc):
+            for e, c in q.t.items():
+                v = c * Q
+                assert v.denominator == 1
+                Wq[midx[e]][uidx[j]] = int(v)
+
+        def sig_bits(n):
+            n = abs(n)
+            while n and n % 2 == 0:
+                n //= 2
+            return n.bit_length()
+
+        if any(sig_bits(v) > 8 or abs(v) >= 2 ** 15 for row in Wq for v in row):
+            return None
+        return {"Q": int(Q), "rows": len(mons), "Wq": Wq}
+
+    def _emit_mfma(self) -> List[str]:
+        nm = self.spec.name
+        form = self.mfma_form()
+        L = ["// matrix-core form of the sub-region polynomial: the monomial coefficients",
+             "// are A = (Wq c) / kQ, Wq an integer matrix exact in bfloat16 (rows: the",
+             "// monomials in the order of A, padded to 64; columns: union taps, padded",
+             "// to 32); value/value_grad take Q A and return unscaled results",
+             "struct %s_mfma {" % nm]
+        if form is None:
+            L += ["  static constexpr bool kOk = false;", "};", ""]
+            return L
+        loc, uidx, mons, midx = self._region_terms(0)
+        fr = self.frames[0]
+        L.append("  static constexpr bool kOk = true;")
+        L.append("  static constexpr int kRows = %d;" % form["rows"])
+        L.append("  static constexpr int kQ = %d;" % form["Q"])
+        L.append("  static constexpr short kWq[64][32] = {%s};" % ", ".join(
+            "{%s}" % ", ".join(str(v) for v in row) for row in form["Wq"]))
+        frame_lines = ["    const float u%d = y%d - %s;" % (i, i, flit(fr[i])) if fr[i] != 0
+                       else "    const float u%d = y%d;" % (i, i) for i in range(3)]
+        L.append("  static __device__ __forceinline__ float value(const float* __restrict__ A, float y0, float y1, float y2) {")
+        L += frame_lines
+        L.append("    return %s;" % horner({e: "A[%d]" % midx[e] for e in mons}, 3, ["u0", "u1", "u2"]))
+        L.append("  }")
+        L.append("  static __device__ __forceinline__ float value_grad(const float* __restrict__ A, float y0, float y1, float y2,")
+        L.append("                                                    float& g0, float& g1, float& g2) {")
+        L += frame_lines
+        for r in range(3):
+            dt = {}
+            for e in mons:
+                if e[r]:
+                    e2 = list(e)
+                    e2[r] -= 1
+                    dt[tuple(e2)] = "A[%d]" % midx[e] if e[r] == 1 else "(A[%d] * %d.0f)" % (midx[e], e[r])
+            L.append("    g%d = %s;" % (r, horner(dt, 3, ["u0", "u1", "u2"])))
+        L.append("    return %s;" % horner({e: "A[%d]" % midx[e] for e in mons}, 3, ["u0", "u1", "u2"]))
+        L.append("  }")
+        L += ["};", ""]
+        return L
+
     def _emit_region(self, k: int) -> List[str]:
         nm = self.spec.name
         d = self.regions[k]
         fr = self.frames[k]
-        loc = [p.translate(fr) for p in d.polys]
-        uidx = [self.union.index(o) for o in d.taps]
+        loc, uidx, mons, midx = self._region_terms(k)
         L = []
-        mons = sorted(set().union(*[set(q.t) for q in loc]), key=lambda e: (-sum(e), e))
-        midx = {e: i for i, e in enumerate(mons)}
         frame_lines = ["  const float u%d = y%d - %s;" % (i, i, flit(fr[i])) if fr[i] != 0
                        else "  const float u%d = y%d;" % (i, i) for i in range(3)]
         # value (monomial coefficients first, then one Horner pass)
@@ -534,8 +625,8 @@ def emit_kind_map(names) -> str:
           "template <int KIND> struct SplineOf;"]
     for nm in names:
         sp = SPECS[nm]
-        L.append("template <> struct SplineOf<%d> { using T = %s_tables; using P = %s_poly; "
-                 "static constexpr const char* kName = \"%s\"; };" % (sp.kind, nm, nm, nm))
+        L.append("template <> struct SplineOf<%d> { using T = %s_tables; using P = %s_poly; using M = %s_mfma; "
+                 "static constexpr const char* kName = \"%s\"; };" % (sp.kind, nm, nm, nm, nm))
     L += ["", "}  // namespace gen", "}  // namespace lsp", ""]
     return "\n".join(L)
 

@@ -136,3 +136,30 @@ def test_transposed_stencil_tables(name):
             n_el += 1
             assert sorted(hit) == list(range(len(union)))
     assert n_el == {"none": 1, "signs": 8, "signed_perm": 48}[tab["symmetry"]]
+
+
+@pytest.mark.parametrize("name", [n for n in ALL if interp.load_tables(n)["mfma"] is not None])
+def test_matrix_core_form_is_exact(name):
+    """The integer weight matrix of the matrix-core path: Wq[m][j] / Q equals
+    the exact rational coefficient of monomial m in tap j's weight polynomial
+    (zero where the tap is not in the sub-region), and every entry has at
+    most 8 significant bits, so it is exact in bf16 and fp16."""
+    tab = interp.load_tables(name)
+    mf = tab["mfma"]
+    Q, Wq, mons = mf["Q"], mf["Wq"], [tuple(e) for e in mf["monomials"]]
+    assert len(mons) == mf["rows"] <= 64 and len(tab["union"]) <= 32
+    reg = tab["regions"][0]
+    expect = [[Fraction(0)] * 32 for _ in range(64)]
+    for w, j in zip(reg["weights"], reg["union_index"]):
+        for key, c in w.items():
+            e = tuple(int(v) for v in key.split(","))
+            expect[mons.index(e)][j] = Fraction(c)
+    for m in range(64):
+        for j in range(32):
+            assert Fraction(Wq[m][j], Q) == expect[m][j], (m, j)
+            v = abs(Wq[m][j])
+            while v and v % 2 == 0:
+                v //= 2
+            assert v.bit_length() <= 8
+            assert float(np.float32(Wq[m][j]).view(np.uint32) & 0xFFFF0000) == float(
+                np.float32(Wq[m][j]).view(np.uint32)), "not exact in bf16"

@@ -71,6 +71,9 @@ def test_unsupported_and_invalid_arguments():
     with pytest.raises(N.LspError) as e:
         sp.debug_geometry((2000, 2000, 2000))
     assert e.value.status == 4
+    assert lib.lsp_set_option(N.LSP_OPT_MFMA, 3) == 1
+    assert lib.lsp_set_option(999, 0) == 1
+    assert lib.lsp_set_option(N.LSP_OPT_MFMA, 2) == 0
 
 
 def _site_offset(tab, geo, n):
