@@ -102,12 +102,12 @@ const char* lsp_version(void);
  * Process-wide evaluation options (take effect for launches issued after the
  * call; not synchronised with launches in flight on other threads).
  *   LSP_OPT_MFMA: how the monomial coefficients A = W c of one-sub-region
- *     splines with more than 16 taps (bcc8) are formed: 0 per-lane FMAs,
- *     1 matrix cores (MFMA) for every coefficient storage, 2 (default, or the
- *     value of LSP_MFMA in the environment) matrix cores for BF16/FP16
- *     storage and per-lane FMAs for FP32.  Every setting gives results within
- *     the FP32 tolerance of the convolution sum; other splines, the dL/dx pass
- *     and batch plans always use per-lane FMAs.
+ *     splines with more than 16 taps (bcc8) are formed: 0 (default, or the
+ *     value of LSP_MFMA in the environment) per-lane FMAs over the generated
+ *     shared-term form of W, 1 matrix cores (MFMA) for every coefficient
+ *     storage, 2 matrix cores for BF16/FP16 storage and FMAs for FP32.  Every
+ *     setting gives results within the FP32 tolerance of the convolution sum;
+ *     other splines, the dL/dx pass and batch plans always use per-lane FMAs.
  * Returns LSP_E_INVALID_ARG for an unknown option or value.
  */
 #define LSP_OPT_MFMA 1

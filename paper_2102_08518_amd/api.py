@@ -46,8 +46,8 @@ def set_option(option: int, value: int) -> None:
 
 def use_mfma(on) -> None:
     """How the monomial coefficients of the splines with a matrix-core form
-    are evaluated: True (matrix cores), False (per-lane FMAs) or "auto"
-    (matrix cores for 16-bit coefficient storage, the default)."""
+    are evaluated: False (per-lane FMAs, the default), True (matrix cores) or
+    "auto" (matrix cores for 16-bit coefficient storage)."""
     set_option(N.LSP_OPT_MFMA, 2 if on == "auto" else (1 if on else 0))
 
 

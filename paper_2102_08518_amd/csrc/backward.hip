@@ -7,14 +7,15 @@
 //   1. key every point by its cell (inactive points get a sentinel key);
 //   2. stable radix sort of (cell, point index)   -- a library sort;
 //   3. cell start offsets by lower-bound search on the sorted keys;
-//   4. per sorted point, the weights g_i w_j(y_i) of every union tap j (the
-//      per-tap polynomials of the reference sub-region), one padded row per
-//      point, and its symmetry id;
-//   5. per cell, partial sums P[u][cell] over the cell's points for every
-//      offset v_u of the symmetry-closed stencil U: a point with symmetry
-//      element G reaches the site cell + v_u through the tap j with
-//      G^T o_j = v_u (generated table J[G][u], inverted to u(G, j));
-//   6. per stored site n, dL/dc_n = sum over u of P[u][n - v_u].
+//   4. per cell, partial sums P[u][cell] over the cell's points (sorted
+//      order) for every offset v_u of the symmetry-closed stencil U: each
+//      point's weights g_i w_j(y_i) (the per-tap polynomials of the reference
+//      sub-region) are formed on the fly, and a point with symmetry element G
+//      reaches the site cell + v_u through the tap j with G^T o_j = v_u
+//      (generated table J[G][u], inverted to u(G, j));
+//   5. per stored site n, dL/dc_n = sum over u of P[u][n - v_u];
+//   6. with dL/dx requested, g_i grad f(x_i) per point, in cell order so that
+//      neighbouring work-items gather neighbouring coefficients.
 // Every sum runs in a fixed order (sorted points, then U), so the result is
 // bit-reproducible.
 #include <hip/hip_runtime.h>
@@ -82,70 +83,40 @@ __global__ __launch_bounds__(kBlk) void k_cell_offsets(const int* __restrict__ k
     }
 }
 
-// Weight row stride (floats): the union stencil rounded up to whole float4s.
-template <int KIND>
-constexpr int row_stride() {
-    return (TablesOf<KIND>::kTaps + 3) / 4 * 4;
-}
-
 template <int KIND>
 __device__ __forceinline__ void tap_weights(const Loc& L, float* w) {
     PolyOf<KIND>::weights(L.y[0], L.y[1], L.y[2], L.region, w);
 }
 
-// Per sorted point: its tap weights g_i w_j(y_i) (one padded row) and
-// symmetry id; with dL_dx, also dL/dx_i = g_i grad f(x_i), computed here in
-// cell order so that neighbouring work-items gather neighbouring
-// coefficients.
-template <int KIND, class CT, class PT, bool DX>
-__global__ __launch_bounds__(kBlk) void k_point_weights(const PT* __restrict__ pts,
-                                                        const int* __restrict__ skeys,
-                                                        const int* __restrict__ svals, int N,
-                                                        int ncell, VolGeom g,
-                                                        const void* __restrict__ coef,
-                                                        unsigned nbytes,
-                                                        const float* __restrict__ gin,
-                                                        float* __restrict__ W,
-                                                        unsigned char* __restrict__ sym,
-                                                        float* __restrict__ dL_dx) {
-    using T = TablesOf<KIND>;
+// dL/dx_i = g_i grad f(x_i) for the sorted points (original index svals[p]).
+template <int KIND, class CT, class PT>
+__global__ __launch_bounds__(kBlk) void k_point_dx(const PT* __restrict__ pts,
+                                                   const int* __restrict__ svals, int N, VolGeom g,
+                                                   const void* __restrict__ coef, unsigned nbytes,
+                                                   const float* __restrict__ gin,
+                                                   float* __restrict__ dL_dx) {
     const int p = blockIdx.x * kBlk + threadIdx.x;
     if (p >= N) return;
     const int i = svals[p];
-    if (DX) eval_point<KIND, CT, PT, kGradX, false>(pts, i, i, coef, nbytes, g, nullptr, dL_dx, gin);
-    if (skeys[p] >= ncell) return;  // inactive: no weights, never read by the gather
-    PT x[3];
-    load_point(pts, i, x);
-    Loc L;
-    locate<KIND>(x, g, L);
-    constexpr int RS = row_stride<KIND>();
-    float w[RS];
-    tap_weights<KIND>(L, w);
-#pragma unroll
-    for (int j = T::kTaps; j < RS; ++j) w[j] = 0.0f;
-    const float gi = gin[i];
-    float4* row = reinterpret_cast<float4*>(W + (size_t)p * RS);
-#pragma unroll
-    for (int q = 0; q < RS / 4; ++q)
-        row[q] = make_float4(gi * w[4 * q], gi * w[4 * q + 1], gi * w[4 * q + 2], gi * w[4 * q + 3]);
-    sym[p] = (unsigned char)sym_id<KIND>(L);
+    eval_point<KIND, CT, PT, kGradX, false>(pts, i, i, coef, nbytes, g, nullptr, dL_dx, gin);
 }
 
 constexpr int kPartBlk = 128;
 
-// P[u][cell] = sum over the cell's points p (sorted order) of the weight of
-// the tap j with G_p^T o_j = v_u.  Each thread owns one cell and keeps its
-// |U| accumulators in LDS (indexed by u(G, j)); every slot has one owner, so
-// the adds happen in program order.
-template <int KIND>
-__global__ __launch_bounds__(kPartBlk) void k_cell_partials(const int* __restrict__ off,
-                                                            const unsigned char* __restrict__ sym,
-                                                            const float* __restrict__ W, int ncell,
+// P[u][cell] = sum over the cell's points p (sorted order) of g_p w_j(y_p)
+// for the tap j with G_p^T o_j = v_u.  Each thread owns one cell and keeps
+// its |U| accumulators in LDS (indexed by u(G, j)); every slot has one owner,
+// so the adds happen in program order and the result is reproducible.
+template <int KIND, class PT>
+__global__ __launch_bounds__(kPartBlk) void k_cell_partials(const PT* __restrict__ pts,
+                                                            const int* __restrict__ svals,
+                                                            const int* __restrict__ off,
+                                                            const float* __restrict__ gin,
+                                                            VolGeom g, int ncell,
                                                             float* __restrict__ P) {
     using T = TablesOf<KIND>;
     constexpr int NU = T::kNumU;
     constexpr int NT = T::kTaps;
-    constexpr int RS = row_stride<KIND>();
     constexpr int SLOTS = NU | 1;   // odd stride between threads' slots
     __shared__ unsigned char Uinv[T::kNumSym * NT];
     __shared__ float acc[kPartBlk * SLOTS];
@@ -160,20 +131,17 @@ __global__ __launch_bounds__(kPartBlk) void k_cell_partials(const int* __restric
     const int c = blockIdx.x * kPartBlk + threadIdx.x;
     const int b = c < ncell ? off[c] : 0, e = c < ncell ? off[c + 1] : 0;
     for (int p = b; p < e; ++p) {
-        const int sg = sym[p];
-        const float4* row = reinterpret_cast<const float4*>(W + (size_t)p * RS);
-        float w[RS];
+        const int i = svals[p];
+        PT x[3];
+        load_point(pts, i, x);
+        Loc L;
+        locate<KIND>(x, g, L);
+        float w[NT];
+        tap_weights<KIND>(L, w);
+        const float gi = gin[i];
+        const unsigned char* ui = Uinv + sym_id<KIND>(L) * NT;
 #pragma unroll
-        for (int q = 0; q < RS / 4; ++q) {
-            const float4 v = row[q];
-            w[4 * q] = v.x;
-            w[4 * q + 1] = v.y;
-            w[4 * q + 2] = v.z;
-            w[4 * q + 3] = v.w;
-        }
-        const unsigned char* ui = Uinv + sg * NT;
-#pragma unroll
-        for (int j = 0; j < NT; ++j) mine[ui[j]] += w[j];
+        for (int j = 0; j < NT; ++j) mine[ui[j]] += gi * w[j];
     }
     if (c >= ncell) return;
     for (int u = 0; u < NU; ++u) P[(size_t)u * ncell + c] = mine[u];
@@ -216,18 +184,11 @@ __global__ __launch_bounds__(kBlk) void k_site_gather(const float* __restrict__ 
 }
 
 struct Layout {
-    size_t keys_in, vals_in, keys_out, vals_out, off, sym, W, P, tmp, total;
+    size_t keys_in, vals_in, keys_out, vals_out, off, P, tmp, total;
     size_t tmp_bytes;
 };
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
-
-int taps_of(int kind) {
-#define LSP_TAPS(k) if (kind == k) return TablesOf<k>::kTaps;
-    LSP_FOR_EACH_KIND(LSP_TAPS)
-#undef LSP_TAPS
-    return 0;
-}
 
 int nu_of(int kind) {
 #define LSP_NU(k) if (kind == k) return TablesOf<k>::kNumU;
@@ -267,8 +228,6 @@ bool layout(int kind, int n_cosets, const int dims[3], int pad, long long N, Lay
     L->keys_out = o; o += nb;
     L->vals_out = o; o += nb;
     L->off = o; o += align256(sizeof(int) * ((size_t)cg.ncell + 1));
-    L->sym = o; o += align256((size_t)n);
-    L->W = o; o += align256(sizeof(float) * (size_t)n * ((taps_of(kind) + 3) / 4 * 4));
     L->P = o; o += align256(sizeof(float) * (size_t)cg.ncell * nu_of(kind));
     L->tmp = o; o += align256(tmp);
     L->tmp_bytes = tmp;
@@ -285,8 +244,6 @@ hipError_t run(const BackwardArgs& a, const Layout& ly) {
     int* keys_out = reinterpret_cast<int*>(ws + ly.keys_out);
     int* vals_out = reinterpret_cast<int*>(ws + ly.vals_out);
     int* off = reinterpret_cast<int*>(ws + ly.off);
-    unsigned char* sym = reinterpret_cast<unsigned char*>(ws + ly.sym);
-    float* W = reinterpret_cast<float*>(ws + ly.W);
     float* P = reinterpret_cast<float*>(ws + ly.P);
     const CellGeom cg = cell_geom(a.dims, a.g.pad, a.n_cosets);
     const int N = a.N;
@@ -310,22 +267,10 @@ hipError_t run(const BackwardArgs& a, const Layout& ly) {
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    if (N > 0) {
-        if (a.dL_dx)
-            hipLaunchKernelGGL((k_point_weights<KIND, CT, PT, true>), dim3(nblk), dim3(kBlk), 0,
-                               a.stream, pts, keys_out, vals_out, N, cg.ncell, a.g, a.coef, a.nbytes,
-                               a.dL_df, W, sym, a.dL_dx);
-        else
-            hipLaunchKernelGGL((k_point_weights<KIND, CT, PT, false>), dim3(nblk), dim3(kBlk), 0,
-                               a.stream, pts, keys_out, vals_out, N, cg.ncell, a.g, a.coef, a.nbytes,
-                               a.dL_df, W, sym, a.dL_dx);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
     {
         const int cblocks = (cg.ncell + kPartBlk - 1) / kPartBlk;
-        hipLaunchKernelGGL((k_cell_partials<KIND>), dim3(cblocks), dim3(kPartBlk), 0, a.stream, off,
-                           sym, W, cg.ncell, P);
+        hipLaunchKernelGGL((k_cell_partials<KIND, PT>), dim3(cblocks), dim3(kPartBlk), 0, a.stream,
+                           pts, vals_out, off, a.dL_df, a.g, cg.ncell, P);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -333,6 +278,9 @@ hipError_t run(const BackwardArgs& a, const Layout& ly) {
     const long long gblocks = (sites + kBlk - 1) / kBlk;
     hipLaunchKernelGGL((k_site_gather<KIND>), dim3((unsigned)gblocks), dim3(kBlk), 0, a.stream, P, cg,
                        a.dims[0], a.dims[1], a.dims[2], a.n_cosets, a.dL_dc);
+    if (N > 0 && a.dL_dx)
+        hipLaunchKernelGGL((k_point_dx<KIND, CT, PT>), dim3(nblk), dim3(kBlk), 0, a.stream, pts,
+                           vals_out, N, a.g, a.coef, a.nbytes, a.dL_df, a.dL_dx);
     (void)sizeof(T);
     return hipGetLastError();
 }

@@ -36,11 +36,12 @@ constexpr int kBinBlk = 1024;
 constexpr int kPtsPerThr = 16;
 constexpr int kCtr = 32;  // ints between consecutive bin counters
 
-template <int KIND, class PT>
-__device__ __forceinline__ int bin_of(const PT x[3], const VolGeom& g, const BinGeom& bg) {
+// Bin of a located point: the block of 2^lb padded coset indices holding its
+// ROE lattice point (coset index floor(k / D)); inactive points go to the
+// sentinel bin nbins.
+template <int KIND>
+__device__ __forceinline__ int bin_index(const Loc& L, const VolGeom& g, const BinGeom& bg) {
     constexpr int D = TablesOf<KIND>::kD;
-    Loc L;
-    locate<KIND>(x, g, L);
     if (!L.active) return bg.nbins;
     int b[3];
     for (int a = 0; a < 3; ++a) {
@@ -48,6 +49,13 @@ __device__ __forceinline__ int bin_of(const PT x[3], const VolGeom& g, const Bin
         b[a] = K >> bg.lb;
     }
     return (b[2] * bg.nb[1] + b[1]) * bg.nb[0] + b[0];
+}
+
+template <int KIND, class PT>
+__device__ __forceinline__ int bin_of(const PT x[3], const VolGeom& g, const BinGeom& bg) {
+    Loc L;
+    locate<KIND>(x, g, L);
+    return bin_index<KIND>(L, g, bg);
 }
 
 // p[t * stride] = 0 for t < n.

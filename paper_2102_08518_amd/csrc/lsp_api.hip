@@ -159,7 +159,7 @@ bool fcc_predicated() {
 }
 
 // Matrix-core evaluation for splines that have it: LSP_OPT_MFMA (0 never,
-// 1 always, 2 for 16-bit coefficient storage), default from LSP_MFMA, else 2.
+// 1 always, 2 for 16-bit coefficient storage), default from LSP_MFMA, else 0.
 std::atomic<int> g_opt_mfma{-1};
 
 bool mfma_for(int ctype) {
@@ -167,8 +167,8 @@ bool mfma_for(int ctype) {
     if (o < 0) {
         static const int v = [] {
             const char* env = getenv("LSP_MFMA");
-            const int x = env ? atoi(env) : 2;
-            return x < 0 || x > 2 ? 2 : x;
+            const int x = env ? atoi(env) : 0;
+            return x < 0 || x > 2 ? 0 : x;
         }();
         o = v;
     }

@@ -142,31 +142,68 @@ template <class CT16> struct StencilParts16 {
 template <> struct StencilParts<bf16_t> : StencilParts16<bf16_t> {};
 template <> struct StencilParts<f16_t> : StencilParts16<f16_t> {};
 
-// Full wavefronts only: every lane of the wave executes this, lanes without
-// a point (valid == false) compute a dummy point and store nothing.
-// Results for the point x go to index o (MODE kValue / kValueGrad).
-template <int KIND, class CT, class PT, int MODE>
-__device__ __forceinline__ void eval_mfma_wave(const PT x[3], int o, bool valid,
-                                               const u32x4_t (&W)[2][2],
-                                               __amdgpu_buffer_rsrc_t r, const VolGeom& g,
-                                               float* __restrict__ out, float* __restrict__ grad) {
+// The point's stencil values already in FP32 registers (zero beyond NTAP),
+// packed the same way: FP32 coefficients split three ways, 16-bit ones
+// re-encoded exactly (the FP32 values are conversions of them).
+template <class CT> struct PackParts;
+template <> struct PackParts<float> {
+    template <int NT, int NTAP>
+    static __device__ __forceinline__ void pack(const float* c, unsigned (*v)[NT / 2]) {
+#pragma unroll
+        for (int j = 0; j < NT; j += 2) {
+            unsigned u0[2], u1[2], u2[2];
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const float cj = j + e < NTAP ? c[j + e] : 0.0f;
+                const unsigned u = __builtin_bit_cast(unsigned, cj);
+                const float r1 = cj - __builtin_bit_cast(float, u & 0xffff0000u);
+                const unsigned v1 = __builtin_bit_cast(unsigned, r1);
+                const float r2 = r1 - __builtin_bit_cast(float, v1 & 0xffff0000u);
+                u0[e] = u;
+                u1[e] = v1;
+                u2[e] = __builtin_bit_cast(unsigned, r2);
+            }
+            v[0][j / 2] = pack_hi16(u0[0], u0[1]);
+            v[1][j / 2] = pack_hi16(u1[0], u1[1]);
+            v[2][j / 2] = pack_hi16(u2[0], u2[1]);
+        }
+    }
+};
+template <> struct PackParts<bf16_t> {
+    template <int NT, int NTAP>
+    static __device__ __forceinline__ void pack(const float* c, unsigned (*v)[NT / 2]) {
+#pragma unroll
+        for (int j = 0; j < NT; j += 2) {
+            const unsigned a = j < NTAP ? __builtin_bit_cast(unsigned, c[j]) : 0u;
+            const unsigned b = j + 1 < NTAP ? __builtin_bit_cast(unsigned, c[j + 1]) : 0u;
+            v[0][j / 2] = pack_hi16(a, b);
+        }
+    }
+};
+template <> struct PackParts<f16_t> {
+    template <int NT, int NTAP>
+    static __device__ __forceinline__ void pack(const float* c, unsigned (*v)[NT / 2]) {
+#pragma unroll
+        for (int j = 0; j < NT; j += 2) {
+            const unsigned a = j < NTAP ? __builtin_bit_cast(unsigned short, (_Float16)c[j]) : 0u;
+            const unsigned b = j + 1 < NTAP ? __builtin_bit_cast(unsigned short, (_Float16)c[j + 1]) : 0u;
+            v[0][j / 2] = a | (b << 16);
+        }
+    }
+};
+
+// Matrix products, results back to one point per lane, polynomial and store
+// for a located point whose packed stencil values are v.  Every lane of the
+// wave executes this; lanes with valid == false store nothing.
+template <int KIND, class CT, int MODE>
+__device__ __forceinline__ void mfma_finish(const Loc& L, unsigned (*v)[16], int o, bool valid,
+                                            const u32x4_t (&W)[2][2], float* __restrict__ out,
+                                            float* __restrict__ grad) {
     using T = TablesOf<KIND>;
     using M = MfmaOf<KIND>;
-    constexpr int NT = 32;                        // taps padded to two K-steps
     constexpr int NS = (T::kTaps + 15) / 16;      // K-steps used
     constexpr int NR = (M::kRows + 31) / 32;      // row tiles used
     constexpr int NP = StencilParts<CT>::kParts;
-
-    Loc L;
-    locate<KIND>(x, g, L);
-    int off[NT];
-#pragma unroll
-    for (int j = 0; j < NT; ++j)
-        off[j] = j < T::kTaps ? tap_offset<KIND>(L, T::kOff[j][0], T::kOff[j][1], T::kOff[j][2],
-                                                 T::kParity[j])
-                              : 0;
-    unsigned v[NP][NT / 2];
-    StencilParts<CT>::template build<NT, T::kTaps>(r, off, v);
 
     // B operands: group 0 = points of lanes 0..31, group 1 = lanes 32..63.
     f32x16_t acc[2][NR];
@@ -228,6 +265,30 @@ __device__ __forceinline__ void eval_mfma_wave(const PT x[3], int o, bool valid,
             for (int a = 0; a < 3; ++a) grad[3 * (size_t)o + a] = L.active ? gx[a] : fill;
         }
     }
+}
+
+// One point per lane, taps gathered from the coefficient buffer.  Full
+// wavefronts only: lanes without a point (valid == false) compute a dummy
+// point and store nothing.  Results for the point x go to index o.
+template <int KIND, class CT, class PT, int MODE>
+__device__ __forceinline__ void eval_mfma_wave(const PT x[3], int o, bool valid,
+                                               const u32x4_t (&W)[2][2],
+                                               __amdgpu_buffer_rsrc_t r, const VolGeom& g,
+                                               float* __restrict__ out, float* __restrict__ grad) {
+    using T = TablesOf<KIND>;
+    constexpr int NT = 32;  // taps padded to two K-steps
+    constexpr int NP = StencilParts<CT>::kParts;
+    Loc L;
+    locate<KIND>(x, g, L);
+    int off[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+        off[j] = j < T::kTaps ? tap_offset<KIND>(L, T::kOff[j][0], T::kOff[j][1], T::kOff[j][2],
+                                                 T::kParity[j])
+                              : 0;
+    unsigned v[NP][NT / 2];
+    StencilParts<CT>::template build<NT, T::kTaps>(r, off, v);
+    mfma_finish<KIND, CT, MODE>(L, v, o, valid, W, out, grad);
 }
 
 template <int KIND, class CT>

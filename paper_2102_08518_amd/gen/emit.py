@@ -157,6 +157,62 @@ def lin_comb(pairs: List[Tuple[str, F]]) -> str:
     return expr
 
 
+def cse_pairs(rows: List[Dict[str, F]]):
+    """Greedy common-subexpression elimination for a linear map.
+
+    rows[m] maps input names to exact coefficients (row m = sum_v w_v v).  A
+    temporary t = v_i + r v_j replaces the pair (v_i, v_j) in every row where
+    both occur with coefficient ratio w_j / w_i = r; the pair occurring in the
+    most rows is taken first, until no pair occurs twice.  Returns the
+    temporaries [(name, v_i, v_j, r)] in evaluation order and the rewritten
+    rows (over inputs and temporaries).  The rewriting is exact: expanding
+    the temporaries gives back the original rows (checked here)."""
+    rows = [dict(r) for r in rows]
+    temps = []
+    while True:
+        cnt: Dict[Tuple[str, str, F], int] = {}
+        for r in rows:
+            items = sorted(r.items())
+            for a in range(len(items)):
+                for b in range(a + 1, len(items)):
+                    (vi, wi), (vj, wj) = items[a], items[b]
+                    key = (vi, vj, wj / wi)
+                    cnt[key] = cnt.get(key, 0) + 1
+        if not cnt:
+            break
+        best = max(cnt.items(), key=lambda kv: (kv[1], -abs(kv[0][2].numerator) - kv[0][2].denominator))
+        (vi, vj, ratio), n = best
+        if n < 2:
+            break
+        t = "t%d" % len(temps)
+        temps.append((t, vi, vj, ratio))
+        for r in rows:
+            if vi in r and vj in r and r[vj] / r[vi] == ratio:
+                w = r.pop(vi)
+                r.pop(vj)
+                r[t] = w
+    return temps, rows
+
+
+def cse_expand(temps, rows):
+    """Inverse of cse_pairs: rows over the original inputs only."""
+    defs: Dict[str, Dict[str, F]] = {}
+    for t, vi, vj, ratio in temps:
+        d: Dict[str, F] = {}
+        for v, w in ((vi, F(1)), (vj, ratio)):
+            for u, x in (defs[v].items() if v in defs else ((v, F(1)),)):
+                d[u] = d.get(u, F(0)) + w * x
+        defs[t] = d
+    out = []
+    for r in rows:
+        e: Dict[str, F] = {}
+        for v, w in r.items():
+            for u, x in (defs[v].items() if v in defs else ((v, F(1)),)):
+                e[u] = e.get(u, F(0)) + w * x
+        out.append({u: x for u, x in e.items() if x != 0})
+    return out
+
+
 # ----------------------------------------------------------- emission
 
 class SplineCode:
@@ -274,14 +330,11 @@ class SplineCode:
             return {"eval": w + contract, "weights": w + nt}
         out = {}
         ev = 0
-        for d, fr in zip(self.regions, self.frames):
-            loc = [p.translate(fr) for p in d.polys]
-            mons = set()
-            for q in loc:
-                mons |= set(q.t)
-            ev += sum(len(q.t) for q in loc) + len(mons)
+        for k in range(len(self.regions)):
+            temps, rows = self._coef_cse(k)
+            ev += len(temps) + sum(len(r) for r in rows) + len(rows)
         out["eval"] = ev
-        out["weights"] = sum(self.nnz)
+        out["weights"] = sum(min(self._weights_cost(k)) for k in range(len(self.regions)))
         return out
 
     # -- code
@@ -361,6 +414,51 @@ class SplineCode:
         uidx = [self.union.index(o) for o in d.taps]
         mons = sorted(set().union(*[set(q.t) for q in loc]), key=lambda e: (-sum(e), e))
         return loc, uidx, mons, {e: i for i, e in enumerate(mons)}
+
+    def _coef_cse(self, k: int):
+        """Monomial coefficients of sub-region k (row m = A[m], over the
+        fetched values c[j] of the union stencil) after pair elimination."""
+        loc, uidx, mons, midx = self._region_terms(k)
+        rows = [{"c[%d]" % uidx[j]: q.t[e] for j, q in enumerate(loc) if e in q.t} for e in mons]
+        temps, new = cse_pairs(rows)
+        assert cse_expand(temps, new) == [{v: w for v, w in r.items() if w != 0} for r in rows]
+        return temps, new
+
+    def _weights_cost(self, k: int):
+        """(Horner per tap, monomials + shared pairs) operation counts."""
+        mono, temps, rows = self._weights_cse(k)
+        return self.nnz[k], len(mono) - 1 + len(temps) + sum(len(r) for r in rows)
+
+    def _weights_use_cse(self, k: int) -> bool:
+        horner_ops, cse_ops = self._weights_cost(k)
+        return cse_ops < horner_ops
+
+    def _weights_cse(self, k: int):
+        """Per-tap weights of sub-region k as combinations of monomials:
+        the monomials (each a lower one times one coordinate, in order of
+        degree), the pair temporaries and one row per tap."""
+        loc, uidx, mons, midx = self._region_terms(k)
+        name = lambda e: "m%d%d%d" % e
+        need = set(mons)
+        for e in list(need):
+            f = list(e)
+            while sum(f) > 0:   # parents along the first nonzero exponent
+                i = next(a for a in range(3) if f[a] > 0)
+                f[i] -= 1
+                need.add(tuple(f))
+        mono = []
+        for e in sorted(need, key=lambda e: (sum(e), e)):
+            if sum(e) == 0:
+                mono.append((name(e), None, None))
+            else:
+                i = next(a for a in range(3) if e[a] > 0)
+                f = list(e)
+                f[i] -= 1
+                mono.append((name(e), name(tuple(f)), i))
+        rows = [{name(e): c for e, c in q.t.items()} for q in loc]
+        temps, new = cse_pairs(rows)
+        assert cse_expand(temps, new) == [{v: w for v, w in r.items() if w != 0} for r in rows]
+        return mono, temps, new
 
     def mfma_form(self):
         """Integer form of the weight matrix for the matrix-core path.
@@ -449,9 +547,11 @@ class SplineCode:
         L.append("// sub-region %d (%s): %d taps, frame (%s), %d weight terms, cond %.2f"
                  % (k, d.name, len(d.taps), ", ".join(str(x) for x in fr), self.nnz[k], self.cond[k]))
         L.append("__device__ __forceinline__ void %s_coef_r%d(const float* __restrict__ c, float* __restrict__ A) {" % (nm, k))
-        for e in mons:
-            pairs = [("c[%d]" % uidx[j], q.t[e]) for j, q in enumerate(loc) if e in q.t]
-            L.append("  A[%d] = %s;" % (midx[e], lin_comb(pairs)))
+        temps, rows = self._coef_cse(k)
+        for t, vi, vj, ratio in temps:
+            L.append("  const float %s = %s;" % (t, lin_comb([(vi, F(1)), (vj, ratio)])))
+        for m, row in enumerate(rows):
+            L.append("  A[%d] = %s;" % (m, lin_comb(sorted(row.items()))))
         L.append("}")
         L.append("")
         L.append("__device__ __forceinline__ float %s_eval_r%d(const float* __restrict__ c, float y0, float y1, float y2) {" % (nm, k))
@@ -479,14 +579,25 @@ class SplineCode:
         L.append("  return %s;" % horner({e: "A[%d]" % midx[e] for e in mons}, 3, ["u0", "u1", "u2"]))
         L.append("}")
         L.append("")
-        # per-tap weights (union-indexed; taps outside this sub-region get 0)
+        # per-tap weights (union-indexed; taps outside this sub-region get 0):
+        # the monomials once, then every weight as a combination of them with
+        # shared pair terms
         L.append("__device__ __forceinline__ void %s_weights_r%d(float y0, float y1, float y2, float* __restrict__ w) {" % (nm, k))
         L += frame_lines
         for j in range(len(self.union)):
             if j not in uidx:
                 L.append("  w[%d] = 0.0f;" % j)
-        for j, q in enumerate(loc):
-            L.append("  w[%d] = %s;" % (uidx[j], horner({e: flit(c) for e, c in q.t.items()}, 3, ["u0", "u1", "u2"])))
+        if self._weights_use_cse(k):
+            mono, temps, rows = self._weights_cse(k)
+            for name, parent, var in mono:
+                L.append("  const float %s = %s;" % (name, "1.0f" if parent is None else "%s * u%d" % (parent, var)))
+            for t, vi, vj, ratio in temps:
+                L.append("  const float %s = %s;" % (t, lin_comb([(vi, F(1)), (vj, ratio)])))
+            for j, row in enumerate(rows):
+                L.append("  w[%d] = %s;" % (uidx[j], lin_comb(sorted(row.items()))))
+        else:
+            for j, q in enumerate(loc):
+                L.append("  w[%d] = %s;" % (uidx[j], horner({e: flit(c) for e, c in q.t.items()}, 3, ["u0", "u1", "u2"])))
         L.append("}")
         L.append("")
         return L

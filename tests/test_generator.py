@@ -163,3 +163,4 @@ def test_matrix_core_form_is_exact(name):
             assert v.bit_length() <= 8
             assert float(np.float32(Wq[m][j]).view(np.uint32) & 0xFFFF0000) == float(
                 np.float32(Wq[m][j]).view(np.uint32)), "not exact in bf16"
+

@@ -46,7 +46,7 @@ def _check_against_single(vols, pts, grads, val, grad):
             else:
                 assert torch.equal(a, v.eval(p))
     finally:
-        api.use_mfma("auto")
+        api.use_mfma(False)
 
 
 def test_batch_matches_single_volume_and_oracle(device):

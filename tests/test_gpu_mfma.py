@@ -25,7 +25,7 @@ def _stored(c, storage):
 @pytest.fixture
 def restore_mfma():
     yield
-    api.use_mfma("auto")
+    api.use_mfma(False)
 
 
 @pytest.mark.parametrize("storage", ["f32", "bf16", "f16"])
