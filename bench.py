@@ -139,7 +139,7 @@ def main():
         f = out.double().cpu().numpy()
         res[storage] = dict(ms=ms, pts_per_s=n / (ms * 1e-3), f=f, path=best)
 
-    # forward + backward (dL/dc, dL/dx) for an MSE loss against the field
+    # forward + backward (dL/dc, dL/dx) of a loss with a given dL/df
     fb = None
     try:
         g = torch.empty(n, dtype=torch.float32, device=dev).uniform_(-1e-6, 1e-6)
@@ -151,8 +151,10 @@ def main():
         wsf, _, _ = vol._binned_ws(xt, None)
 
         def step_fb():
-            vol.eval(xt, out, binned=fwd_binned, workspace=wsf)
-            vol.backward(xt, g, want_dc=True, want_dx=True, workspace=ws)
+            # forward: value and point gradient; backward: dL/dc, and dL/dx
+            # from the saved gradient
+            _, grad = vol.eval_grad(xt, binned=fwd_binned, workspace=wsf)
+            vol.backward(xt, g, want_dc=True, want_dx=True, workspace=ws, grad_f=grad)
 
         ms_fb = time_fn(step_fb, max(args.steps // 5, 3), 2, stream)
         fb = dict(ms=ms_fb, pts_per_s=n / (ms_fb * 1e-3))

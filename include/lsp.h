@@ -226,6 +226,21 @@ lsp_status lsp_backward(const lsp_volume* vol, const void* pts, lsp_dtype pts_dt
                         const float* dL_df, float* dL_dc, float* dL_dx, void* workspace,
                         size_t ws_bytes, hipStream_t stream);
 
+/*
+ * dL/dx_i = dL_df[i] * grad_f[i] from gradients saved by lsp_eval_grad or
+ * lsp_eval_binned (the chain rule through the query point; the gradient of
+ * f is the derivative of the reference sub-region polynomial mapped back by
+ * the symmetry transform, Sec. 3 and 4.2).  Gives exactly what lsp_backward
+ * writes to dL_dx for the same points, without evaluating the spline again:
+ * a training step that needs dL/dx computes value and gradient in its
+ * forward pass and calls this, and lsp_backward only for dL/dc.
+ *   dL_df   device, N floats;  grad_f  device, N*3 floats (f's gradient);
+ *   dL_dx   device, N*3 floats, overwritten (may be the same array as grad_f).
+ * NaN gradients (NaN points) stay NaN.  Allocates nothing.
+ */
+lsp_status lsp_backward_dx_from_grad(int64_t N, const float* dL_df, const float* grad_f,
+                                     float* dL_dx, hipStream_t stream);
+
 /* --------------------------------------------------------------- batches */
 
 typedef struct lsp_batch_plan lsp_batch_plan;  /* opaque: bound work list + captured graph */

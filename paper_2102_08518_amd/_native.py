@@ -22,7 +22,8 @@ EXPORTS = ("lsp_status_string", "lsp_last_error", "lsp_version", "lsp_set_option
            "lsp_spline_destroy", "lsp_spline_get_info", "lsp_volume_create", "lsp_volume_destroy",
            "lsp_volume_info", "lsp_volume_set_coeffs", "lsp_eval", "lsp_eval_grad",
            "lsp_eval_binned_workspace_size", "lsp_eval_binned",
-           "lsp_backward_workspace_size", "lsp_backward", "lsp_batch_plan_create",
+           "lsp_backward_workspace_size", "lsp_backward", "lsp_backward_dx_from_grad",
+           "lsp_batch_plan_create",
            "lsp_batch_plan_info", "lsp_batch_run", "lsp_batch_plan_destroy",
            "lsp_debug_tap_offsets", "lsp_debug_geometry")
 
@@ -86,6 +87,7 @@ def lib():
             "lsp_backward_workspace_size": (ctypes.c_int, [vp, i64, ctypes.POINTER(ctypes.c_size_t)]),
             "lsp_backward": (ctypes.c_int, [vp, vp, ctypes.c_int, i64, vp, vp, vp, vp,
                                             ctypes.c_size_t, vp]),
+            "lsp_backward_dx_from_grad": (ctypes.c_int, [ctypes.c_int64, vp, vp, vp, vp]),
             "lsp_batch_plan_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                                      ctypes.POINTER(i64), ctypes.POINTER(vp),
                                                      ctypes.POINTER(vp), ctypes.c_int, vp,

@@ -238,14 +238,29 @@ class Volume:
         return b.value
 
     def backward(self, pts: torch.Tensor, dL_df: torch.Tensor, want_dc: bool = True,
-                 want_dx: bool = True, workspace: Optional[torch.Tensor] = None):
-        """(dL/dc as (n_cosets, Z, Y, X) float32 or None, dL/dx as (N, 3) or None)."""
+                 want_dx: bool = True, workspace: Optional[torch.Tensor] = None,
+                 grad_f: Optional[torch.Tensor] = None):
+        """(dL/dc as (n_cosets, Z, Y, X) float32 or None, dL/dx as (N, 3) or None).
+        With grad_f (the (N, 3) gradient from eval_grad of the same points),
+        dL/dx is formed from it (lsp_backward_dx_from_grad) instead of
+        evaluating the spline's gradient again."""
         pts = self._pts(pts)
         n = pts.shape[0]
         g = dL_df.contiguous().to(torch.float32)
         dc = (torch.empty((self.n_cosets,) + self.dims[::-1], dtype=torch.float32,
                           device=pts.device) if want_dc else None)
         dx = torch.empty(n, 3, dtype=torch.float32, device=pts.device) if want_dx else None
+        if want_dx and grad_f is not None:
+            gf = grad_f.contiguous()
+            if gf.shape != (n, 3) or gf.dtype != torch.float32:
+                raise ValueError("grad_f must be a (N, 3) float32 tensor")
+            N.check(N.lib().lsp_backward_dx_from_grad(n, _ptr(g), _ptr(gf), _ptr(dx),
+                                                      _stream(pts.device)))
+            if not want_dc:
+                return dc, dx
+            dx_arg = None
+        else:
+            dx_arg = dx
         wsb = self.workspace_bytes(n) if want_dc else 0
         if wsb and (workspace is None or workspace.numel() < wsb):
             workspace = torch.empty(wsb + 256, dtype=torch.uint8, device=pts.device)
@@ -255,8 +270,10 @@ class Volume:
             ws_ptr = (base + 255) // 256 * 256
             ws_len = workspace.numel() - (ws_ptr - base)
         N.check(N.lib().lsp_backward(self._h, _ptr(pts), _TORCH_DT[pts.dtype], n, _ptr(g), _ptr(dc),
-                                     _ptr(dx), ctypes.c_void_p(ws_ptr), ws_len, _stream(pts.device)))
+                                     _ptr(dx_arg), ctypes.c_void_p(ws_ptr), ws_len,
+                                     _stream(pts.device)))
         return dc, dx
+
 
 class BatchPlan:
     """Many volumes of uneven size evaluated by one persistent launch that
@@ -310,15 +327,22 @@ class LatticeSplineFn(torch.autograd.Function):
     def forward(ctx, pts: torch.Tensor, coeffs: torch.Tensor, vol: Volume):
         vol.set(coeffs.detach())
         ctx.vol = vol
+        if pts.requires_grad:
+            # the gradient with respect to the points comes with the value
+            val, grad = vol.eval_grad(pts.detach())
+            ctx.save_for_backward(pts, grad)
+            return val
         ctx.save_for_backward(pts)
         return vol.eval(pts.detach())
 
     @staticmethod
     def backward(ctx, g: torch.Tensor):
-        (pts,) = ctx.saved_tensors
+        saved = ctx.saved_tensors
+        pts = saved[0]
+        grad_f = saved[1] if len(saved) > 1 else None
         want_dx = ctx.needs_input_grad[0]
         want_dc = ctx.needs_input_grad[1]
-        dc, dx = ctx.vol.backward(pts.detach(), g, want_dc=want_dc, want_dx=want_dx)
+        dc, dx = ctx.vol.backward(pts.detach(), g, want_dc=want_dc, want_dx=want_dx, grad_f=grad_f)
         if dx is not None:
             dx = dx.to(pts.dtype)
         return dx, dc, None

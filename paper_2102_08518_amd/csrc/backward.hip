@@ -147,6 +147,13 @@ __global__ __launch_bounds__(kPartBlk) void k_cell_partials(const PT* __restrict
     for (int u = 0; u < NU; ++u) P[(size_t)u * ncell + c] = mine[u];
 }
 
+// dL/dx from a saved gradient: one thread per output component.
+__global__ __launch_bounds__(kBlk) void k_dx_from_grad(long long n3, const float* __restrict__ gin,
+                                                       const float* grad, float* dL_dx) {
+    const long long t = (long long)blockIdx.x * kBlk + threadIdx.x;
+    if (t < n3) dL_dx[t] = gin[t / 3] * grad[t];
+}
+
 // dL/dc_n = sum_u P[u][n - v_u], one thread per stored site in the canonical
 // coset-major C order of the output.
 template <int KIND>
@@ -307,6 +314,17 @@ size_t backward_workspace_bytes(int kind, int n_cosets, const int64_t dims[3], i
     Layout ly{};
     if (!layout(kind, n_cosets, d, pad, N, &ly)) return (size_t)-1;
     return ly.total;
+}
+
+hipError_t launch_dx_from_grad(long long N, const float* dL_df, const float* grad_f, float* dL_dx,
+                               hipStream_t stream) {
+    if (N <= 0) return hipSuccess;
+    const long long n3 = 3 * N;
+    const long long blocks = (n3 + kBlk - 1) / kBlk;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_dx_from_grad, dim3((unsigned)blocks), dim3(kBlk), 0, stream, n3, dL_df,
+                       grad_f, dL_dx);
+    return hipGetLastError();
 }
 
 hipError_t launch_backward_coef(const BackwardArgs& a) {

@@ -611,6 +611,15 @@ lsp_status lsp_backward(const lsp_volume* vol, const void* pts, lsp_dtype pts_dt
     return LSP_OK;
 }
 
+lsp_status lsp_backward_dx_from_grad(int64_t N, const float* dL_df, const float* grad_f,
+                                     float* dL_dx, hipStream_t stream) {
+    if (N < 0) return fail(LSP_E_SHAPE, "N < 0");
+    if (N > 0 && (!dL_df || !grad_f || !dL_dx)) return fail(LSP_E_INVALID_ARG, "NULL array");
+    hipError_t e = lsp::launch_dx_from_grad(N, dL_df, grad_f, dL_dx, stream);
+    if (e != hipSuccess) return hip_fail(e, "dL/dx launch");
+    return LSP_OK;
+}
+
 // ------------------------------------------------------------ batched plans
 
 }  // extern "C"

@@ -32,4 +32,8 @@ struct BackwardArgs {
 size_t backward_workspace_bytes(int kind, int n_cosets, const int64_t dims[3], int pad, int64_t N);
 hipError_t launch_backward_coef(const BackwardArgs& a);
 
+// dL_dx[3i + a] = dL_df[i] * grad_f[3i + a].
+hipError_t launch_dx_from_grad(long long N, const float* dL_df, const float* grad_f, float* dL_dx,
+                               hipStream_t stream);
+
 }  // namespace lsp

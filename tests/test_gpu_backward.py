@@ -202,3 +202,28 @@ def test_adam_fit_matches_fp64_fit(device):
     gpu_loss, ref_loss = np.array(gpu_loss), np.array(ref_loss)
     assert ref_loss[-1] < 1e-3 * ref_loss[0]
     np.testing.assert_allclose(gpu_loss, ref_loss, rtol=1e-2, atol=1e-7)
+
+
+@pytest.mark.parametrize("name", ["bcc8", "fcc6", "tricubic"])
+def test_dx_from_saved_gradient_matches_backward(device, name):
+    """dL/dx formed from the gradient of eval_grad (lsp_backward_dx_from_grad)
+    is bit-identical to lsp_backward's own dL/dx, NaN points included, and
+    the autograd function that uses it gives the same point gradients."""
+    print("case dx from grad", name, flush=True)
+    vol, c, x, g = _setup(name, 9, 5001, 17, device)
+    x[7] = np.nan
+    xt = torch.tensor(x, device=device)
+    gt = torch.tensor(g, device=device)
+    _, dx_ref = vol.backward(xt, gt, want_dc=False, want_dx=True)
+    _, grad = vol.eval_grad(xt, want_value=False)
+    dc1, dx1 = vol.backward(xt, gt, want_dc=True, want_dx=True, grad_f=grad)
+    dc0, _ = vol.backward(xt, gt, want_dc=True, want_dx=False)
+    assert torch.equal(torch.nan_to_num(dx1, nan=3.0), torch.nan_to_num(dx_ref, nan=3.0))
+    assert torch.isnan(dx1[7]).all()
+    assert torch.equal(dc1, dc0)
+    xg = torch.tensor(np.nan_to_num(x, nan=1.0), device=device, requires_grad=True)
+    ct = torch.tensor(c, device=device, requires_grad=True)
+    f = api.LatticeSplineFn.apply(xg, ct, vol)
+    (f * gt).sum().backward()
+    _, dx2 = vol.backward(xg.detach(), gt, want_dc=False, want_dx=True)
+    assert torch.equal(xg.grad, dx2)
