@@ -217,7 +217,9 @@ lsp_status lsp_backward_workspace_size(const lsp_volume* vol, int64_t N, size_t*
  *          coset-major C-order layout as lsp_volume_set_coeffs' sources:
  *          dL/dc_n = sum_i dL_df[i] * phi(x_i - n).  Overwritten.
  *          Computed without floating-point atomics; bit-reproducible.
- *   dL_dx  (nullable) device, N*3 floats: dL/dx_i = dL_df[i] * grad f(x_i).
+ *   dL_dx  (nullable) device, N*3 floats: dL/dx_i = dL_df[i] * grad f(x_i),
+ *          evaluated in the points' order (lsp_backward_dx_from_grad forms
+ *          the same values from a gradient saved by the forward pass).
  *   workspace, ws_bytes: device scratch of at least
  *          lsp_backward_workspace_size(vol, N) bytes (needed when dL_dc is
  *          requested), aligned to 256 bytes.

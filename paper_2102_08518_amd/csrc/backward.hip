@@ -13,9 +13,7 @@
 //      sub-region) are formed on the fly, and a point with symmetry element G
 //      reaches the site cell + v_u through the tap j with G^T o_j = v_u
 //      (generated table J[G][u], inverted to u(G, j));
-//   5. per stored site n, dL/dc_n = sum over u of P[u][n - v_u];
-//   6. with dL/dx requested, g_i grad f(x_i) per point, in cell order so that
-//      neighbouring work-items gather neighbouring coefficients.
+//   5. per stored site n, dL/dc_n = sum over u of P[u][n - v_u].
 // Every sum runs in a fixed order (sorted points, then U), so the result is
 // bit-reproducible.
 #include <hip/hip_runtime.h>
@@ -88,19 +86,6 @@ __device__ __forceinline__ void tap_weights(const Loc& L, float* w) {
     PolyOf<KIND>::weights(L.y[0], L.y[1], L.y[2], L.region, w);
 }
 
-// dL/dx_i = g_i grad f(x_i) for the sorted points (original index svals[p]).
-template <int KIND, class CT, class PT>
-__global__ __launch_bounds__(kBlk) void k_point_dx(const PT* __restrict__ pts,
-                                                   const int* __restrict__ svals, int N, VolGeom g,
-                                                   const void* __restrict__ coef, unsigned nbytes,
-                                                   const float* __restrict__ gin,
-                                                   float* __restrict__ dL_dx) {
-    const int p = blockIdx.x * kBlk + threadIdx.x;
-    if (p >= N) return;
-    const int i = svals[p];
-    eval_point<KIND, CT, PT, kGradX, false>(pts, i, i, coef, nbytes, g, nullptr, dL_dx, gin);
-}
-
 constexpr int kPartBlk = 128;
 
 // P[u][cell] = sum over the cell's points p (sorted order) of g_p w_j(y_p)
@@ -147,11 +132,16 @@ __global__ __launch_bounds__(kPartBlk) void k_cell_partials(const PT* __restrict
     for (int u = 0; u < NU; ++u) P[(size_t)u * ncell + c] = mine[u];
 }
 
-// dL/dx from a saved gradient: one thread per output component.
-__global__ __launch_bounds__(kBlk) void k_dx_from_grad(long long n3, const float* __restrict__ gin,
+// dL/dx from a saved gradient: one thread per point.
+__global__ __launch_bounds__(kBlk) void k_dx_from_grad(int N, const float* __restrict__ gin,
                                                        const float* grad, float* dL_dx) {
-    const long long t = (long long)blockIdx.x * kBlk + threadIdx.x;
-    if (t < n3) dL_dx[t] = gin[t / 3] * grad[t];
+    const int i = blockIdx.x * kBlk + threadIdx.x;
+    if (i >= N) return;
+    const float gi = gin[i];
+    const float a = grad[3 * (size_t)i], b = grad[3 * (size_t)i + 1], c = grad[3 * (size_t)i + 2];
+    dL_dx[3 * (size_t)i] = gi * a;
+    dL_dx[3 * (size_t)i + 1] = gi * b;
+    dL_dx[3 * (size_t)i + 2] = gi * c;
 }
 
 // dL/dc_n = sum_u P[u][n - v_u], one thread per stored site in the canonical
@@ -285,9 +275,6 @@ hipError_t run(const BackwardArgs& a, const Layout& ly) {
     const long long gblocks = (sites + kBlk - 1) / kBlk;
     hipLaunchKernelGGL((k_site_gather<KIND>), dim3((unsigned)gblocks), dim3(kBlk), 0, a.stream, P, cg,
                        a.dims[0], a.dims[1], a.dims[2], a.n_cosets, a.dL_dc);
-    if (N > 0 && a.dL_dx)
-        hipLaunchKernelGGL((k_point_dx<KIND, CT, PT>), dim3(nblk), dim3(kBlk), 0, a.stream, pts,
-                           vals_out, N, a.g, a.coef, a.nbytes, a.dL_df, a.dL_dx);
     (void)sizeof(T);
     return hipGetLastError();
 }
@@ -319,10 +306,9 @@ size_t backward_workspace_bytes(int kind, int n_cosets, const int64_t dims[3], i
 hipError_t launch_dx_from_grad(long long N, const float* dL_df, const float* grad_f, float* dL_dx,
                                hipStream_t stream) {
     if (N <= 0) return hipSuccess;
-    const long long n3 = 3 * N;
-    const long long blocks = (n3 + kBlk - 1) / kBlk;
-    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_dx_from_grad, dim3((unsigned)blocks), dim3(kBlk), 0, stream, n3, dL_df,
+    if (N > 0x7fffffffLL) return hipErrorInvalidValue;
+    const int n = (int)N;
+    hipLaunchKernelGGL(k_dx_from_grad, dim3((n + kBlk - 1) / kBlk), dim3(kBlk), 0, stream, n, dL_df,
                        grad_f, dL_dx);
     return hipGetLastError();
 }

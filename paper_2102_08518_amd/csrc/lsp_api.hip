@@ -576,7 +576,7 @@ lsp_status lsp_backward(const lsp_volume* vol, const void* pts, lsp_dtype pts_dt
     lsp_status st = check_eval_args(vol, pts, pts_dtype, N);
     if (st) return st;
     if (N > 0 && !dL_df && (dL_dc || dL_dx)) return fail(LSP_E_INVALID_ARG, "dL_df is NULL");
-    if (dL_dx && !dL_dc && N > 0) {
+    if (dL_dx && N > 0) {
         st = run_eval(vol, pts, pts_dtype, N, lsp::kGradX, nullptr, dL_dx, dL_df, stream);
         if (st) return st;
     }
@@ -597,11 +597,8 @@ lsp_status lsp_backward(const lsp_volume* vol, const void* pts, lsp_dtype pts_dt
         b.g = vol->geom;
         b.n_cosets = vol->def.n_cosets;
         for (int a = 0; a < 3; ++a) b.dims[a] = (int)vol->dims[a];
-        b.coef = vol->buf;
-        b.nbytes = (unsigned)vol->nbytes;
         b.dL_df = dL_df;
         b.dL_dc = dL_dc;
-        b.dL_dx = N > 0 ? dL_dx : nullptr;
         b.ws = workspace;
         b.ws_bytes = ws_bytes;
         b.stream = stream;

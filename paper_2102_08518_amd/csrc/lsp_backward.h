@@ -19,11 +19,8 @@ struct BackwardArgs {
     VolGeom g;
     int n_cosets;
     int dims[3];
-    const void* coef;      // internal coefficient buffer (for dL/dx)
-    unsigned nbytes;
     const float* dL_df;
     float* dL_dc;
-    float* dL_dx;          // nullable: computed in cell order together with the weights
     void* ws;
     size_t ws_bytes;
     hipStream_t stream;
