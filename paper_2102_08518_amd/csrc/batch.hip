@@ -1,13 +1,15 @@
-// Batched evaluation of many volumes of uneven size in one persistent launch.
+// Batched evaluation of many volumes of uneven size in a few persistent
+// launches.
 //
 // A plan binds the per-volume descriptors (coefficient buffer, layout,
-// points, outputs) and a work list of (volume, tile of points) items.  One
-// grid of persistent workgroups pops items from an atomic counter until the
-// list is exhausted; inside an item the spline kind, storage type and mode
-// are uniform, so the per-point body of the single-volume kernel runs
-// without divergence.  The counter is reset by a one-thread kernel that runs
-// first on the same stream, so the pair can be captured in a graph and
-// replayed.
+// points, outputs) and a work list of (volume, tile of points) items, grouped
+// by kernel variant (spline kind, storage type, value or value+gradient).
+// Per group one grid of persistent workgroups pops items from the group's
+// atomic counter until its list is exhausted; each variant is its own
+// instantiation, so it keeps the registers of the single-volume kernel
+// instead of the union of all variants.  The counters are reset by a
+// one-thread kernel that runs first on the same stream, so the launches can
+// be captured in a graph and replayed.
 #include <hip/hip_runtime.h>
 
 #include "lsp_batch.h"
@@ -19,35 +21,20 @@ namespace {
 
 constexpr int kBatchBlock = 256;
 
-__global__ void k_batch_reset(int* counter) { *counter = 0; }
+__global__ void k_batch_reset(int* counters, int n) {
+    for (int i = 0; i < n; ++i) counters[i] = 0;
+}
 
 template <int KIND, class CT, int MODE>
 __device__ __forceinline__ void run_item(const BatchVol& v, int start, int count) {
     const int end = start + count;
+#pragma unroll 1
     for (int p = start + (int)threadIdx.x; p < end; p += kBatchBlock)
         eval_point<KIND, CT, float, MODE, false>(v.pts, p, p, v.coef, v.nbytes, v.g, v.val, v.grad,
                                                  nullptr);
 }
 
-template <int KIND>
-__device__ __forceinline__ void run_kind(const BatchVol& v, int start, int count) {
-    const bool grad = v.grad != nullptr;
-    switch (v.ctype) {
-        case kCF32:
-            if (grad) run_item<KIND, float, kValueGrad>(v, start, count);
-            else run_item<KIND, float, kValue>(v, start, count);
-            break;
-        case kCBF16:
-            if (grad) run_item<KIND, bf16_t, kValueGrad>(v, start, count);
-            else run_item<KIND, bf16_t, kValue>(v, start, count);
-            break;
-        default:
-            if (grad) run_item<KIND, f16_t, kValueGrad>(v, start, count);
-            else run_item<KIND, f16_t, kValue>(v, start, count);
-            break;
-    }
-}
-
+template <int KIND, class CT, int MODE>
 __global__ __launch_bounds__(kBatchBlock) void k_batch(const BatchVol* __restrict__ vols,
                                                        const BatchItem* __restrict__ items,
                                                        int n_items, int* __restrict__ counter) {
@@ -55,30 +42,60 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch(const BatchVol* __restric
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
         __syncthreads();
-        const int it = s_item;
+        // uniform across the workgroup: the item and volume descriptors are
+        // then loaded once into scalar registers
+        const int it = __builtin_amdgcn_readfirstlane(s_item);
         __syncthreads();
-        if (it >= n_items) break;  // uniform across the workgroup
+        if (it >= n_items) break;
         const BatchItem w = items[it];
-        const BatchVol v = vols[w.vol];
-        switch (v.kind) {
-#define LSP_CASE(k) case k: run_kind<k>(v, w.start, w.count); break;
-            LSP_FOR_EACH_KIND(LSP_CASE)
-#undef LSP_CASE
-        }
+        // by reference: the layout fields selected per axis are then read
+        // from the descriptor in memory, not from a private copy
+        const BatchVol& v = vols[w.vol];
+        run_item<KIND, CT, MODE>(v, w.start, w.count);
     }
+}
+
+template <int KIND, class CT>
+hipError_t launch_group_ct(const BatchVol* vols, const BatchItem* items, const BatchGroup& gr,
+                           int* counter, int blocks, hipStream_t stream) {
+    const int b = blocks < gr.count ? blocks : gr.count;
+    if (gr.grad)
+        hipLaunchKernelGGL((k_batch<KIND, CT, kValueGrad>), dim3(b), dim3(kBatchBlock), 0, stream,
+                           vols, items + gr.first, gr.count, counter);
+    else
+        hipLaunchKernelGGL((k_batch<KIND, CT, kValue>), dim3(b), dim3(kBatchBlock), 0, stream, vols,
+                           items + gr.first, gr.count, counter);
+    return hipGetLastError();
+}
+
+template <int KIND>
+hipError_t launch_group(const BatchVol* vols, const BatchItem* items, const BatchGroup& gr,
+                        int* counter, int blocks, hipStream_t stream) {
+    switch (gr.ctype) {
+        case kCF32: return launch_group_ct<KIND, float>(vols, items, gr, counter, blocks, stream);
+        case kCBF16: return launch_group_ct<KIND, bf16_t>(vols, items, gr, counter, blocks, stream);
+        case kCF16: return launch_group_ct<KIND, f16_t>(vols, items, gr, counter, blocks, stream);
+    }
+    return hipErrorInvalidValue;
 }
 
 }  // namespace
 
-hipError_t launch_batch(const BatchVol* vols, const BatchItem* items, int n_items, int* counter,
-                        int blocks, hipStream_t stream) {
-    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, stream, counter);
+hipError_t launch_batch(const BatchVol* vols, const BatchItem* items, const BatchGroup* groups,
+                        int n_groups, int* counters, int blocks, hipStream_t stream) {
+    if (n_groups <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, stream, counters, n_groups);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (n_items <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_batch, dim3(blocks), dim3(kBatchBlock), 0, stream, vols, items, n_items,
-                       counter);
-    return hipGetLastError();
+    for (int gi = 0; gi < n_groups && e == hipSuccess; ++gi) {
+        const BatchGroup& gr = groups[gi];
+        if (gr.count <= 0) continue;
+        e = hipErrorInvalidValue;
+#define LSP_GROUP(k) \
+        if (gr.kind == k) e = launch_group<k>(vols, items, gr, counters + gi, blocks, stream);
+        LSP_FOR_EACH_KIND(LSP_GROUP)
+#undef LSP_GROUP
+    }
+    return e;
 }
 
 int batch_block_threads() { return kBatchBlock; }

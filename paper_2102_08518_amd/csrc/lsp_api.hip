@@ -629,7 +629,8 @@ struct lsp_batch_plan {
     int device = 0;
     lsp::BatchVol* d_vols = nullptr;
     lsp::BatchItem* d_items = nullptr;
-    int* d_counter = nullptr;
+    std::vector<lsp::BatchGroup> groups;   // host copy, launch order
+    int* d_counter = nullptr;              // one per group
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -640,14 +641,33 @@ namespace {
 std::mutex g_tune_mu;
 std::map<std::string, std::pair<int, int>> g_tune_cache;  // signature -> (tile, blocks/CU)
 
-std::vector<lsp::BatchItem> make_items(const std::vector<lsp::BatchVol>& hv, int tile) {
+// Items grouped by kernel variant (kind, storage, value / value+gradient),
+// groups with the most points first; inside a group the largest volumes
+// first, so their many tiles are handed out before the tail.
+std::vector<lsp::BatchItem> make_items(const std::vector<lsp::BatchVol>& hv, int tile,
+                                       std::vector<lsp::BatchGroup>* groups) {
+    auto key = [&](int v) { return (hv[v].kind * 3 + hv[v].ctype) * 2 + (hv[v].grad ? 1 : 0); };
+    std::map<int, long long> work;
+    for (size_t v = 0; v < hv.size(); ++v) work[key((int)v)] += hv[v].N;
     std::vector<int> order(hv.size());
     for (size_t v = 0; v < hv.size(); ++v) order[v] = (int)v;
-    // largest volumes first: their many tiles are handed out before the tail
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return hv[a].N > hv[b].N; });
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        const int ka = key(a), kb = key(b);
+        if (ka != kb) return work[ka] != work[kb] ? work[ka] > work[kb] : ka < kb;
+        return hv[a].N > hv[b].N;
+    });
     std::vector<lsp::BatchItem> items;
-    for (int v : order)
+    groups->clear();
+    int cur = -1;
+    for (int v : order) {
+        if (hv[v].N == 0) continue;
+        if (key(v) != cur) {
+            cur = key(v);
+            groups->push_back({hv[v].kind, hv[v].ctype, hv[v].grad ? 1 : 0, (int)items.size(), 0});
+        }
         for (int s = 0; s < hv[v].N; s += tile) items.push_back({v, s, std::min(tile, hv[v].N - s)});
+        groups->back().count = (int)items.size() - groups->back().first;
+    }
     return items;
 }
 
@@ -715,7 +735,8 @@ lsp_status lsp_batch_plan_create(int n_vol, const lsp_volume* const* vols, const
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device);
     if (e != hipSuccess) { destroy_plan(p); return hip_fail(e, "device query"); }
     e = hipMalloc(&p->d_vols, sizeof(lsp::BatchVol) * n_vol);
-    if (e == hipSuccess) e = hipMalloc(&p->d_counter, sizeof(int));
+    // one counter per possible variant (kinds x storages x modes)
+    if (e == hipSuccess) e = hipMalloc(&p->d_counter, sizeof(int) * lsp::gen::kNumKinds * 3 * 2);
     if (e != hipSuccess) { destroy_plan(p); return fail(LSP_E_OOM, "hipMalloc: %s", hipGetErrorString(e)); }
     e = hipMemcpy(p->d_vols, hv.data(), sizeof(lsp::BatchVol) * n_vol, hipMemcpyHostToDevice);
     if (e != hipSuccess) { destroy_plan(p); return hip_fail(e, "hipMemcpy(vols)"); }
@@ -741,15 +762,17 @@ lsp_status lsp_batch_plan_create(int n_vol, const lsp_volume* const* vols, const
         (void)hipEventCreate(&t1);
         float best = 1e30f;
         for (int ti = 0; ti < 3; ++ti) {
-            std::vector<lsp::BatchItem> items = make_items(hv, tiles[ti]);
+            std::vector<lsp::BatchItem> items = make_items(hv, tiles[ti], &p->groups);
             lsp_status st = upload_items(p, items);
             if (st) { (void)hipEventDestroy(t0); (void)hipEventDestroy(t1); destroy_plan(p); return st; }
             for (int bi = 0; bi < 3; ++bi) {
                 const int blocks = std::max(1, std::min(ncu * bpcs[bi], p->n_items));
-                e = lsp::launch_batch(p->d_vols, p->d_items, p->n_items, p->d_counter, blocks, stream);
+                e = lsp::launch_batch(p->d_vols, p->d_items, p->groups.data(), (int)p->groups.size(),
+                                      p->d_counter, blocks, stream);
                 if (e == hipSuccess) e = hipEventRecord(t0, stream);
                 for (int r = 0; r < 3 && e == hipSuccess; ++r)
-                    e = lsp::launch_batch(p->d_vols, p->d_items, p->n_items, p->d_counter, blocks, stream);
+                    e = lsp::launch_batch(p->d_vols, p->d_items, p->groups.data(),
+                                          (int)p->groups.size(), p->d_counter, blocks, stream);
                 if (e == hipSuccess) e = hipEventRecord(t1, stream);
                 if (e == hipSuccess) e = hipEventSynchronize(t1);
                 float ms = 0;
@@ -768,7 +791,7 @@ lsp_status lsp_batch_plan_create(int n_vol, const lsp_volume* const* vols, const
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune_cache[sig] = {tile, bpc};
     }
-    std::vector<lsp::BatchItem> items = make_items(hv, tile);
+    std::vector<lsp::BatchItem> items = make_items(hv, tile, &p->groups);
     lsp_status st = upload_items(p, items);
     if (st) { destroy_plan(p); return st; }
     p->tile = tile;
@@ -777,7 +800,8 @@ lsp_status lsp_batch_plan_create(int n_vol, const lsp_volume* const* vols, const
     e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t el = lsp::launch_batch(p->d_vols, p->d_items, p->n_items, p->d_counter, p->blocks, p->cap);
+        hipError_t el = lsp::launch_batch(p->d_vols, p->d_items, p->groups.data(),
+                                          (int)p->groups.size(), p->d_counter, p->blocks, p->cap);
         e = hipStreamEndCapture(p->cap, &p->graph);
         if (e == hipSuccess) e = el;
     }

@@ -25,10 +25,21 @@ struct BatchItem {
     int count;
 };
 
-// Reset the work counter, then run the persistent kernel with `blocks`
-// workgroups.  Both are plain kernel launches (graph-capturable).
-hipError_t launch_batch(const BatchVol* vols, const BatchItem* items, int n_items, int* counter,
-                        int blocks, hipStream_t stream);
+// The items of one kernel variant (spline kind, storage, value or
+// value+gradient): a contiguous range of the item list.
+struct BatchGroup {
+    int kind;
+    int ctype;
+    int grad;
+    int first;
+    int count;
+};
+
+// Reset the groups' work counters (device, n_groups ints), then run one
+// persistent kernel per group with at most `blocks` workgroups.  All are
+// plain kernel launches (graph-capturable); groups is host memory.
+hipError_t launch_batch(const BatchVol* vols, const BatchItem* items, const BatchGroup* groups,
+                        int n_groups, int* counters, int blocks, hipStream_t stream);
 int batch_block_threads();
 
 }  // namespace lsp
