@@ -63,6 +63,65 @@ def measured_traffic(kernel_path: str):
     return entry["bytes_per_launch"]
 
 
+def write_traffic(fetch_dir: str, write_dir: str) -> dict:
+    """profiles/traffic.json from two rocprofv3 counter runs of this script
+    (--pmc FETCH_SIZE and --pmc WRITE_SIZE, each with --copy-probe): every
+    kernel's average counter value scaled by what the same counter reads for
+    the 256 MiB device copy, as HBM bytes per launch (per step for the binned
+    path: its binning kernels plus the evaluation)."""
+    import collections
+    import csv
+
+    def load(d, counter):
+        agg = collections.defaultdict(list)
+        copy = 0.0
+        with open(os.path.join(d, "run_counter_collection.csv")) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] != counter:
+                    continue
+                v = float(r["Counter_Value"])
+                if r["Kernel_Name"].startswith("__amd_rocclr_copyBuffer"):
+                    copy = max(copy, v)   # the probe is the largest copy
+                else:
+                    agg[r["Kernel_Name"]].append(v)
+        return {k: sum(v) / len(v) for k, v in agg.items()}, copy
+
+    fe, cf = load(fetch_dir, "FETCH_SIZE")
+    wr, cw = load(write_dir, "WRITE_SIZE")
+    probe_kib = 262144.0
+    sf, sw = probe_kib / cf, probe_kib / cw
+
+    def per_launch(prefix):
+        def one(d):
+            ks = [k for k in d if k.startswith(prefix)]
+            if len(ks) != 1:
+                raise RuntimeError("kernel %r: %d matches" % (prefix, len(ks)))
+            return d[ks[0]]
+        return one(fe) * sf * 1024.0, one(wr) * sw * 1024.0
+
+    direct = per_launch("void lsp::k_eval<1, float, float, 0, false>")
+    prep = ["lsp::(anonymous namespace)::k_zero", "void lsp::(anonymous namespace)::k_bin_count<1, float>",
+            "lsp::(anonymous namespace)::k_bin_scan", "void lsp::(anonymous namespace)::k_bin_scatter<float>"]
+    bf = bw = 0.0
+    for k in prep:
+        f, w = per_launch(k)
+        bf += f
+        bw += w
+    ef, ew = per_launch("void lsp::(anonymous namespace)::k_eval_binned<1, float, float, 0>")
+    out = {"source_hash": kernel_source_hash(),
+           "note": "HBM bytes per launch (per step for the binned path: binning kernels + evaluation) "
+                   "of the BCC 2x64^3 / 2^22-point forward, FP32 coefficients; FETCH_SIZE x %.3f, "
+                   "WRITE_SIZE x %.3f (the 256 MiB device copy reads %.0f / %.0f KiB)" % (sf, sw, cf, cw),
+           "bcc8_f32_direct": {"bytes_per_launch": round(direct[0] + direct[1]),
+                               "fetch": round(direct[0]), "write": round(direct[1])},
+           "bcc8_f32_binned": {"bytes_per_launch": round(bf + bw + ef + ew), "fetch": round(bf + ef),
+                               "write": round(bw + ew), "eval_kernel_fetch": round(ef),
+                               "eval_kernel_write": round(ew)}}
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
+        json.dump(out, fh, indent=1)
+    return out
+
+
 def time_fn(fn, steps, warmup, stream):
     import torch
     for _ in range(warmup):
@@ -88,7 +147,13 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device-to-device copy (a kernel of known traffic "
                          "that calibrates hardware byte counters)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/traffic.json from the rocprofv3 output directories of a "
+                         "--pmc FETCH_SIZE and a --pmc WRITE_SIZE run of this script (no GPU)")
     args = ap.parse_args()
+    if args.traffic_from:
+        print(json.dumps(write_traffic(*args.traffic_from), indent=1))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the evaluation runs on a single device "
               "(--gpus %d requested)." % args.gpus, file=sys.stderr)
