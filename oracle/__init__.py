@@ -54,7 +54,10 @@ def _load():
                                               ctypes.c_int, i32p, i32p, i64p, ctypes.c_int64,
                                               f64p, f64p, f64p]
             lib.orc_num_threads.argtypes = []
-            for f in (lib.orc_phi, lib.orc_eval, lib.orc_backward_coef, lib.orc_num_threads):
+            lib.orc_eval_hess.argtypes = [ctypes.c_int, ctypes.c_int, i32p, i32p, ctypes.c_int, i32p,
+                                          i32p, i64p, f64p, ctypes.c_int64, f64p, f64p, f64p, f64p]
+            for f in (lib.orc_phi, lib.orc_eval, lib.orc_eval_hess, lib.orc_backward_coef,
+                      lib.orc_num_threads):
                 f.restype = ctypes.c_int
             _lib = lib
     return _lib
@@ -175,6 +178,27 @@ def evaluate(spline: Spline, dims, coeffs, x, grad: bool = False, brute: bool = 
     if rc:
         raise RuntimeError("orc_eval failed: %d" % rc)
     return (f, g) if grad else f
+
+
+def evaluate_hessian(spline: Spline, dims, coeffs, x):
+    """f(x), grad f and the Hessian of f ((N, s, s)) for per-coset coefficient
+    arrays; only for box splines that stay C^1 after removing any direction
+    (the derivative identity applied twice)."""
+    lib = _load()
+    D, dims = _layout_args(spline, dims)
+    flat = _coef_flat(spline, coeffs, dims)
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(-1, spline.s))
+    f = np.empty(x.shape[0])
+    g = np.empty_like(x)
+    h = np.empty((x.shape[0], spline.s, spline.s))
+    rc = lib.orc_eval_hess(spline.s, spline.Xi.shape[1], _p(spline.Xi, ctypes.c_int32),
+                           _p(spline.L, ctypes.c_int32), spline.n_cosets, _p(D, ctypes.c_int32),
+                           _p(spline.shifts, ctypes.c_int32), _p(dims, ctypes.c_int64),
+                           _p(flat, ctypes.c_double), x.shape[0], _p(x, ctypes.c_double),
+                           _p(f, ctypes.c_double), _p(g, ctypes.c_double), _p(h, ctypes.c_double))
+    if rc:
+        raise RuntimeError("orc_eval_hess failed: %d" % rc)
+    return f, g, h
 
 
 def backward(spline: Spline, dims, x, g_out):

@@ -37,7 +37,13 @@
  *
  * Gradients use the directional-derivative identity
  *   D_xi M_Xi(z) = M_{Xi\xi}(z) - M_{Xi\xi}(z - xi)
- * for s independent directions, followed by an s x s solve.
+ * for s independent directions, followed by an s x s solve.  Hessians apply
+ * it twice: grad(D_xi M_Xi) = grad M_{Xi\xi}(z) - grad M_{Xi\xi}(z - xi),
+ * the inner gradients by the same solve on Xi\xi, then H = A^{-1} R with A
+ * the s chosen directions as rows and R the rows grad(D_xi M_Xi).  This needs
+ * Xi with every two directions removed still spanning (C^1 box splines and
+ * smoother), where the sub-region polynomials' second derivatives are the
+ * classical ones off the knot planes.
  *
  * Stored coefficients are described per Cartesian coset (the lookup of Sec. 4.1
  * is one memory array per Cartesian coset): coset m holds the sites
@@ -271,6 +277,89 @@ static double phi_eval(const orc_spline *sp, const double *y, double *grad, memo
     return val;
 }
 
+/* Up to s directions of Xi(mult), mutually independent, whose removal keeps
+ * Xi spanning; their indices in dirs, their vectors as the rows of A. */
+static int pick_dirs(const orc_spline *sp, const int *mult, int dirs[3], double A[3][3]) {
+    const int s = sp->s;
+    int rows = 0;
+    int sub[ORC_MAXD];
+    for (int d = 0; d < sp->nd && rows < s; ++d) {
+        if (!mult[d]) continue;
+        memcpy(sub, mult, sizeof(int) * sp->nd);
+        sub[d] -= 1;
+        if (!spans(sp, sub)) continue;
+        double T[3][3];
+        for (int r = 0; r < rows; ++r)
+            for (int i = 0; i < s; ++i) T[r][i] = A[r][i];
+        for (int i = 0; i < s; ++i) T[rows][i] = sp->dir[d][i];
+        if (rows + 1 == s) {
+            if (detn(s, T) == 0.0) continue;
+        } else if (rows == 1 && s == 3) {
+            double cx = T[0][1] * T[1][2] - T[0][2] * T[1][1];
+            double cy = T[0][2] * T[1][0] - T[0][0] * T[1][2];
+            double cz = T[0][0] * T[1][1] - T[0][1] * T[1][0];
+            if (cx == 0.0 && cy == 0.0 && cz == 0.0) continue;
+        }
+        for (int i = 0; i < s; ++i) A[rows][i] = sp->dir[d][i];
+        dirs[rows++] = d;
+    }
+    return rows;
+}
+
+/* grad M_{Xi(mult)}(z - shift) by s directional derivatives; 0 if Xi(mult)
+ * has no s usable directions. */
+static int box_grad(const orc_spline *sp, const int *mult, const int *shift, const double *z,
+                    memo_t *memo, double g[3]) {
+    const int s = sp->s;
+    int dirs[3];
+    double A[3][3], b[3];
+    if (pick_dirs(sp, mult, dirs, A) != s) return 0;
+    int sub[ORC_MAXD];
+    for (int r = 0; r < s; ++r) {
+        const int d = dirs[r];
+        memcpy(sub, mult, sizeof(int) * sp->nd);
+        sub[d] -= 1;
+        int sh[3] = {shift[0], shift[1], shift[2]};
+        for (int i = 0; i < s; ++i) sh[i] += sp->dir[d][i];
+        b[r] = box_M(sp, sub, shift, z, memo) - box_M(sp, sub, sh, z, memo);
+    }
+    g[0] = g[1] = g[2] = 0.0;
+    return solve(s, A, b, g);
+}
+
+/* phi(y), grad phi and the Hessian of phi (s x s, row-major); 0 if the
+ * Hessian is not available for this Xi. */
+static int phi_hess(const orc_spline *sp, const double *y, double *val, double *grad,
+                    double *hess, memo_t *memo) {
+    const int s = sp->s;
+    *val = phi_eval(sp, y, grad, memo);
+    double z[3] = {0, 0, 0};
+    int zero[3] = {0, 0, 0};
+    for (int i = 0; i < s; ++i) z[i] = y[i] + sp->centre[i];
+    int dirs[3];
+    double A[3][3], R[3][3];
+    if (pick_dirs(sp, sp->mult0, dirs, A) != s) return 0;
+    int sub[ORC_MAXD];
+    for (int r = 0; r < s; ++r) {
+        const int d = dirs[r];
+        memcpy(sub, sp->mult0, sizeof(int) * sp->nd);
+        sub[d] -= 1;
+        int sh[3] = {0, 0, 0};
+        for (int i = 0; i < s; ++i) sh[i] = sp->dir[d][i];
+        double g0[3], g1[3];
+        if (!box_grad(sp, sub, zero, z, memo, g0) || !box_grad(sp, sub, sh, z, memo, g1)) return 0;
+        for (int i = 0; i < s; ++i) R[r][i] = sp->detL * (g0[i] - g1[i]);
+    }
+    /* A H = R, column by column */
+    for (int j = 0; j < s; ++j) {
+        double b[3], h[3] = {0, 0, 0};
+        for (int r = 0; r < s; ++r) b[r] = R[r][j];
+        if (!solve(s, A, b, h)) return 0;
+        for (int i = 0; i < s; ++i) hess[i * s + j] = h[i];
+    }
+    return 1;
+}
+
 /* ----------------------------------------------------------- set-up */
 
 /* Xi: s x n row-major, columns are directions.  L: s x s. */
@@ -476,6 +565,72 @@ int orc_eval(int s, int n, const int *Xi, const int *L, int n_cosets, const int 
                 f[p] = c.f;
                 if (grad)
                     for (int i = 0; i < s; ++i) grad[p * s + i] = c.g[i];
+            }
+        }
+        free(memo.tab);
+    }
+    return err;
+}
+
+/* f, grad f and the Hessian of f (npts x s x s) at npts points x; returns
+ * -30 when the Hessian is not available for this Xi (two directions whose
+ * removal stops Xi spanning). */
+int orc_eval_hess(int s, int n, const int *Xi, const int *L, int n_cosets, const int *D,
+                  const int *shifts, const int64_t *dims, const double *coef, int64_t npts,
+                  const double *x, double *f, double *grad, double *hess) {
+    orc_spline sp;
+    orc_layout ly;
+    int rc = spline_init(&sp, s, n, Xi, L);
+    if (rc) return rc;
+    rc = layout_init(&ly, s, n_cosets, D, shifts, dims);
+    if (rc) return rc - 20;
+    int err = 0;
+#pragma omp parallel
+    {
+        memo_t memo = memo_new();
+        if (!memo.tab) {
+#pragma omp atomic write
+            err = -10;
+        } else {
+#pragma omp for schedule(dynamic, 16)
+            for (int64_t p = 0; p < npts; ++p) {
+                const double *xp = x + p * s;
+                double fa = 0.0, ga[3] = {0, 0, 0}, ha[9] = {0};
+                for (int m = 0; m < ly.n_cosets; ++m) {
+                    int64_t lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+                    int empty = 0;
+                    for (int i = 0; i < s; ++i) {
+                        double a = (xp[i] - sp.halfwidth[i] - ly.shift[m][i]) / ly.D[i];
+                        double b = (xp[i] + sp.halfwidth[i] - ly.shift[m][i]) / ly.D[i];
+                        if (!(a == a) || !(b == b)) { empty = 1; break; }
+                        if (a < -1e15) a = -1e15;
+                        if (b > 1e15) b = 1e15;
+                        lo[i] = (int64_t)ceil(a);
+                        hi[i] = (int64_t)floor(b);
+                        if (lo[i] < 0) lo[i] = 0;
+                        if (hi[i] > ly.dims[i] - 1) hi[i] = ly.dims[i] - 1;
+                    }
+                    if (empty) continue;
+                    for (int64_t k = lo[2]; k <= hi[2]; ++k)
+                        for (int64_t j = lo[1]; j <= hi[1]; ++j)
+                            for (int64_t i = lo[0]; i <= hi[0]; ++i) {
+                                int64_t idx[3] = {i, j, k};
+                                double y[3] = {0, 0, 0}, g[3] = {0, 0, 0}, h[9] = {0}, v = 0.0;
+                                for (int a = 0; a < s; ++a)
+                                    y[a] = xp[a] - (double)(ly.D[a] * idx[a] + ly.shift[m][a]);
+                                if (!phi_hess(&sp, y, &v, g, h, &memo)) {
+#pragma omp atomic write
+                                    err = -30;
+                                }
+                                const double cn = coef[m * ly.per_coset + (k * ly.dims[1] + j) * ly.dims[0] + i];
+                                fa += cn * v;
+                                for (int a = 0; a < s; ++a) ga[a] += cn * g[a];
+                                for (int a = 0; a < s * s; ++a) ha[a] += cn * h[a];
+                            }
+                }
+                f[p] = fa;
+                for (int a = 0; a < s; ++a) grad[p * s + a] = ga[a];
+                for (int a = 0; a < s * s; ++a) hess[p * s * s + a] = ha[a];
             }
         }
         free(memo.tab);

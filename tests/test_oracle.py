@@ -386,3 +386,88 @@ def test_backward_x_is_g_times_grad():
     dx = oracle.backward_x(sp, dims, coeffs, x, g)
     _, gr = oracle.evaluate(sp, dims, coeffs, x, grad=True)
     np.testing.assert_allclose(dx, g[:, None] * gr, atol=1e-15)
+
+
+# ------------------------------------------------------------ Hessians
+
+HESS = [TRICUBIC, BCC8, FCC6, TRIQUADRATIC]   # C^1 and smoother after removing a direction
+
+
+def test_tricubic_hessian_closed_form():
+    """phi's Hessian for the tensor-product cubic B-spline: products of the
+    textbook first and second derivatives of the centred cubic B-spline."""
+    def d1(t):
+        a = np.abs(t)
+        return np.sign(t) * np.where(a <= 1, -2 * a + 1.5 * a ** 2, np.where(a <= 2, -0.5 * (2 - a) ** 2, 0))
+
+    def d2(t):
+        a = np.abs(t)
+        return np.where(a <= 1, -2 + 3 * a, np.where(a <= 2, 2 - a, 0))
+
+    E = 9
+    dims = (E,) * 3
+    coeffs = [np.zeros((E, E, E))]
+    coeffs[0][4, 4, 4] = 1.0          # phi(x - n), n = (4, 4, 4)
+    y = rng.uniform(-2.3, 2.3, (300, 3))
+    _, _, H = oracle.evaluate_hessian(TRICUBIC, dims, coeffs, y + 4.0)
+    b = [beta3(y[:, i]) for i in range(3)]
+    g = [d1(y[:, i]) for i in range(3)]
+    h = [d2(y[:, i]) for i in range(3)]
+    ref = np.zeros((y.shape[0], 3, 3))
+    for i in range(3):
+        for j in range(3):
+            f = [b[0], b[1], b[2]]
+            if i == j:
+                f[i] = h[i]
+            else:
+                f[i], f[j] = g[i], g[j]
+            ref[:, i, j] = f[0] * f[1] * f[2]
+    np.testing.assert_allclose(H, ref, atol=1e-12)
+
+
+@pytest.mark.parametrize("sp", HESS)
+def test_hessian_symmetric_and_matches_gradient_differences(sp):
+    E = 8
+    dims = (E,) * 3
+    coeffs = [rng.uniform(-1, 1, (E, E, E)) for _ in range(sp.n_cosets)]
+    x = _interior(sp, E, 20)
+    f, g, H = oracle.evaluate_hessian(sp, dims, coeffs, x)
+    f0, g0 = oracle.evaluate(sp, dims, coeffs, x, grad=True)
+    np.testing.assert_allclose(f, f0, atol=1e-14)
+    np.testing.assert_allclose(g, g0, atol=1e-13)
+    np.testing.assert_allclose(H, H.transpose(0, 2, 1), atol=1e-12)
+    h = 1e-5
+    fd = np.zeros_like(H)
+    for a in range(3):
+        e = np.zeros(3)
+        e[a] = h
+        fd[:, :, a] = (oracle.evaluate(sp, dims, coeffs, x + e, grad=True)[1]
+                       - oracle.evaluate(sp, dims, coeffs, x - e, grad=True)[1]) / (2 * h)
+    np.testing.assert_allclose(H, fd, atol=1e-7)
+
+
+@pytest.mark.parametrize("sp", HESS)
+def test_hessian_exact_for_quadratic_data(sp):
+    """c_n = n^T Q n + b.n + a gives f = q(x) + const for these splines
+    (quadratics are reproduced up to the second-moment constant), so the
+    Hessian is exactly 2Q."""
+    E = 10
+    dims = (E,) * 3
+    pos = oracle.site_positions(sp, dims).astype(np.float64)
+    Q = np.array([[0.3, -0.1, 0.05], [-0.1, -0.2, 0.15], [0.05, 0.15, 0.4]])
+    b = np.array([0.2, -0.3, 0.1])
+    vals = np.einsum("ni,ij,nj->n", pos, Q, pos) + pos @ b + 1.0
+    coeffs = [c.reshape(E, E, E) for c in vals.reshape(sp.n_cosets, -1)]
+    x = _interior(sp, E, 30)
+    _, _, H = oracle.evaluate_hessian(sp, dims, coeffs, x)
+    np.testing.assert_allclose(H, np.broadcast_to(2 * Q, H.shape), atol=1e-10)
+
+
+def test_hessian_refused_for_c0_splines():
+    """Removing two directions of the trilinear / linear BCC splines stops
+    them spanning: no classical Hessian, and the oracle says so."""
+    E = 6
+    for sp in (TRILINEAR, BCC4):
+        coeffs = [np.ones((E, E, E)) for _ in range(sp.n_cosets)]
+        with pytest.raises(RuntimeError):
+            oracle.evaluate_hessian(sp, (E,) * 3, coeffs, np.full((1, 3), 5.3))
