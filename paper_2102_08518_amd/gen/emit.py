@@ -579,6 +579,36 @@ class SplineCode:
         L.append("  return %s;" % horner({e: "A[%d]" % midx[e] for e in mons}, 3, ["u0", "u1", "u2"]))
         L.append("}")
         L.append("")
+        # value, gradient and Hessian (h: d2/du0du0, du0du1, du0du2, du1du1,
+        # du1du2, du2du2)
+        L.append("__device__ __forceinline__ float %s_eval_hess_r%d(const float* __restrict__ c, float y0, float y1, float y2," % (nm, k))
+        L.append("                                                float& g0, float& g1, float& g2, float* __restrict__ h) {")
+        L += frame_lines
+        L.append("  float A[%d];" % len(mons))
+        L.append("  %s_coef_r%d(c, A);" % (nm, k))
+        for r in range(3):
+            dt = {}
+            for e in mons:
+                if e[r]:
+                    e2 = list(e)
+                    e2[r] -= 1
+                    dt[tuple(e2)] = "A[%d]" % midx[e] if e[r] == 1 else "(A[%d] * %d.0f)" % (midx[e], e[r])
+            L.append("  g%d = %s;" % (r, horner(dt, 3, ["u0", "u1", "u2"])))
+        for hi_, (r, q) in enumerate([(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]):
+            dt = {}
+            for e in mons:
+                e2 = list(e)
+                k1 = e2[r]
+                e2[r] -= 1
+                k2 = e2[q]
+                e2[q] -= 1
+                if k1 > 0 and k2 > 0:
+                    mult = k1 * k2
+                    dt[tuple(e2)] = "A[%d]" % midx[e] if mult == 1 else "(A[%d] * %d.0f)" % (midx[e], mult)
+            L.append("  h[%d] = %s;" % (hi_, horner(dt, 3, ["u0", "u1", "u2"])))
+        L.append("  return %s;" % horner({e: "A[%d]" % midx[e] for e in mons}, 3, ["u0", "u1", "u2"]))
+        L.append("}")
+        L.append("")
         # per-tap weights (union-indexed; taps outside this sub-region get 0):
         # the monomials once, then every weight as a combination of them with
         # shared pair terms
@@ -609,12 +639,14 @@ class SplineCode:
         taps1 = [sorted(f) for f in fac]
         for i in range(3):
             L.append("// axis %d: 1D weights at offsets %s on [0,1)" % (i, taps1[i]))
-            L.append("__device__ __forceinline__ void %s_w1d_%d(float t, float* w, float* dw) {" % (nm, i))
+            L.append("__device__ __forceinline__ void %s_w1d_%d(float t, float* w, float* dw, float* ddw = nullptr) {" % (nm, i))
             for a, o in enumerate(taps1[i]):
                 q = fac[i][o]
                 L.append("  w[%d] = %s;" % (a, horner({e: flit(c) for e, c in q.t.items()}, 1, ["t"])))
                 dq = q.deriv(0)
                 L.append("  if (dw) dw[%d] = %s;" % (a, horner({e: flit(c) for e, c in dq.t.items()}, 1, ["t"])))
+                ddq = dq.deriv(0)
+                L.append("  if (ddw) ddw[%d] = %s;" % (a, horner({e: flit(c) for e, c in ddq.t.items()}, 1, ["t"])))
             L.append("}")
             L.append("")
         n0, n1, n2 = (len(t) for t in taps1)
@@ -665,6 +697,39 @@ class SplineCode:
         L.append("  return f;")
         L.append("}")
         L.append("")
+        # value, gradient and Hessian: contractions with the 1D weights of
+        # derivative orders (ox, oy, oz), ox + oy + oz <= 2
+        L.append("__device__ __forceinline__ float %s_eval_hess_r0(const float* __restrict__ c, float y0, float y1, float y2," % nm)
+        L.append("                                                float& g0, float& g1, float& g2, float* __restrict__ h) {")
+        L.append("  float wx[3][%d], wy[3][%d], wz[3][%d];" % (n0, n1, n2))
+        L.append("  %s_w1d_0(y0, wx[0], wx[1], wx[2]); %s_w1d_1(y1, wy[0], wy[1], wy[2]); %s_w1d_2(y2, wz[0], wz[1], wz[2]);" % (nm, nm, nm))
+        orders = [(ox, oy, oz) for ox in range(3) for oy in range(3) for oz in range(3) if ox + oy + oz <= 2]
+        pairs = sorted(set((ox, oy) for ox, oy, _ in orders))
+        L.append("  float F[%d] = {};" % len(orders))
+        for cc in range(n2):
+            L.append("  {")
+            L.append("    float r[%d] = {};" % len(pairs))
+            for b in range(n1):
+                sums = []
+                for ox in range(3):
+                    e = "c[%d] * wx[%d][0]" % (cidx(0, b, cc), ox)
+                    for a in range(1, n0):
+                        e = "fmaf(c[%d], wx[%d][%d], %s)" % (cidx(a, b, cc), ox, a, e)
+                    sums.append(e)
+                L.append("    { const float s0 = %s, s1 = %s, s2 = %s;" % tuple(sums))
+                for pi, (ox, oy) in enumerate(pairs):
+                    L.append("      r[%d] = fmaf(s%d, wy[%d][%d], r[%d]);" % (pi, ox, oy, b, pi))
+                L.append("    }")
+            for oi, (ox, oy, oz) in enumerate(orders):
+                L.append("    F[%d] = fmaf(r[%d], wz[%d][%d], F[%d]);" % (oi, pairs.index((ox, oy)), oz, cc, oi))
+            L.append("  }")
+        oid = {o: i for i, o in enumerate(orders)}
+        L.append("  g0 = F[%d]; g1 = F[%d]; g2 = F[%d];" % (oid[(1, 0, 0)], oid[(0, 1, 0)], oid[(0, 0, 1)]))
+        L.append("  h[0] = F[%d]; h[1] = F[%d]; h[2] = F[%d]; h[3] = F[%d]; h[4] = F[%d]; h[5] = F[%d];" % (
+            oid[(2, 0, 0)], oid[(1, 1, 0)], oid[(1, 0, 1)], oid[(0, 2, 0)], oid[(0, 1, 1)], oid[(0, 0, 2)]))
+        L.append("  return F[%d];" % oid[(0, 0, 0)])
+        L.append("}")
+        L.append("")
         # weights
         L.append("__device__ __forceinline__ void %s_weights_r0(float y0, float y1, float y2, float* __restrict__ w) {" % nm)
         L.append("  float wx[%d], wy[%d], wz[%d];" % (n0, n1, n2))
@@ -712,6 +777,22 @@ def _emit_poly_struct_impl(nm: str, nreg: int) -> List[str]:
               "    }",
               "    if (region) return %s_eval_grad_r1(c, y0, y1, y2, g0, g1, g2);" % nm,
               "    return %s_eval_grad_r0(c, y0, y1, y2, g0, g1, g2);" % nm, "  }"]
+    L += ["  template <bool PRED>",
+          "  static __device__ __forceinline__ float value_grad_hess(const float* __restrict__ c, float y0, float y1, float y2, int region,",
+          "                                                         float& g0, float& g1, float& g2, float* __restrict__ h) {"]
+    if nreg == 1:
+        L += ["    (void)region;", "    return %s_eval_hess_r0(c, y0, y1, y2, g0, g1, g2, h);" % nm, "  }"]
+    else:
+        L += ["    if (PRED) {",
+              "      float a0, a1, a2, b0, b1, b2, ha[6], hb[6];",
+              "      const float v0 = %s_eval_hess_r0(c, y0, y1, y2, a0, a1, a2, ha);" % nm,
+              "      const float v1 = %s_eval_hess_r1(c, y0, y1, y2, b0, b1, b2, hb);" % nm,
+              "      g0 = region ? b0 : a0; g1 = region ? b1 : a1; g2 = region ? b2 : a2;",
+              "      for (int i = 0; i < 6; ++i) h[i] = region ? hb[i] : ha[i];",
+              "      return region ? v1 : v0;",
+              "    }",
+              "    if (region) return %s_eval_hess_r1(c, y0, y1, y2, g0, g1, g2, h);" % nm,
+              "    return %s_eval_hess_r0(c, y0, y1, y2, g0, g1, g2, h);" % nm, "  }"]
     L += ["  static __device__ __forceinline__ void weights(float y0, float y1, float y2, int region, float* __restrict__ w) {"]
     if nreg == 1:
         L += ["    (void)region;", "    %s_weights_r0(y0, y1, y2, w);" % nm, "  }"]
