@@ -22,7 +22,7 @@
  *   * The caller owns every buffer it passes in; the library never frees
  *     them.  The library owns its handles and the internal coefficient
  *     buffer of a volume; each is released by the matching *_destroy call.
- *   * lsp_eval, lsp_eval_grad and lsp_backward allocate nothing: scratch
+ *   * lsp_eval, lsp_eval_grad, lsp_eval_hessian and lsp_backward allocate nothing: scratch
  *     space of the backward pass is a caller-provided workspace.
  *   * Handles are immutable between lsp_volume_set_coeffs calls, so several
  *     threads or streams may evaluate one volume concurrently.
@@ -76,7 +76,8 @@ typedef struct lsp_volume lsp_volume;  /* opaque: a spline plus bound coefficien
 
 typedef struct lsp_spline_info {
     int s;                 /* dimension (3) */
-    int kind;              /* 0 tricubic on Z^3, 1 BCC 8-direction, 2 FCC 6-direction */
+    int kind;              /* 0 tricubic on Z^3, 1 BCC 8-direction, 2 FCC 6-direction,
+                              3 trilinear, 4 BCC linear (4-direction), 5 triquadratic */
     int n_cosets;          /* Cartesian cosets of the lattice */
     int D[3];              /* coset scale */
     int shift[4][3];       /* coset shifts (first n_cosets rows used) */
@@ -87,6 +88,8 @@ typedef struct lsp_spline_info {
     int radius;            /* max |component| of a stencil offset, lattice units */
     int fma_eval;          /* FMAs of the generated value code, per point */
     int pad;               /* zero halo of the internal layout, coset units */
+    int continuity;        /* phi is C^continuity: the fewest directions whose
+                              removal leaves Xi not spanning, minus 2 (Sec. 2) */
 } lsp_spline_info;
 
 /* Human-readable name of a status; never NULL. */
@@ -189,6 +192,24 @@ lsp_status lsp_eval(const lsp_volume* vol, const void* pts, lsp_dtype pts_dtype,
  */
 lsp_status lsp_eval_grad(const lsp_volume* vol, const void* pts, lsp_dtype pts_dtype, int64_t N,
                          float* val, float* grad, hipStream_t stream);
+
+/*
+ * Value, gradient and Hessian: hess[6i..6i+5] = the second partials
+ * (xx, xy, xz, yy, yz, zz) of f at x_i; val[i] = f(x_i) and grad[3i+a] =
+ * df/dx_a (x_i) as for lsp_eval_grad, each skipped when NULL.  The Hessian is
+ * that of the sub-region polynomial carried back through the symmetry
+ * transform: for y = G (x - k) with G a signed permutation it is G^T H_y G
+ * (Sec. 3 applies to every derivative of the reference polynomial).  Where
+ * phi is only C^1 (triquadratic) the second partials jump across sub-region
+ * boundaries and the value of the sub-region the point is assigned to is
+ * returned.  Requires continuity >= 1 (lsp_spline_info): for the C^0 splines
+ * (trilinear, BCC linear) it returns LSP_E_UNSUPPORTED before queueing work.
+ * A NaN point gives NaN in every output, a point outside the stored lattice
+ * zeros.  Allocates nothing.
+ *   hess       device, N*6 floats (required when N > 0).
+ */
+lsp_status lsp_eval_hessian(const lsp_volume* vol, const void* pts, lsp_dtype pts_dtype,
+                            int64_t N, float* val, float* grad, float* hess, hipStream_t stream);
 
 /*
  * The same results as lsp_eval (val) and lsp_eval_grad (grad, nullable), bit

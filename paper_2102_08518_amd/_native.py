@@ -21,7 +21,7 @@ STATUS = {0: "LSP_OK", 1: "LSP_E_INVALID_ARG", 2: "LSP_E_UNSUPPORTED", 3: "LSP_E
 EXPORTS = ("lsp_status_string", "lsp_last_error", "lsp_version", "lsp_set_option", "lsp_spline_create",
            "lsp_spline_destroy", "lsp_spline_get_info", "lsp_volume_create", "lsp_volume_destroy",
            "lsp_volume_info", "lsp_volume_set_coeffs", "lsp_eval", "lsp_eval_grad",
-           "lsp_eval_binned_workspace_size", "lsp_eval_binned",
+           "lsp_eval_hessian", "lsp_eval_binned_workspace_size", "lsp_eval_binned",
            "lsp_backward_workspace_size", "lsp_backward", "lsp_backward_dx_from_grad",
            "lsp_batch_plan_create",
            "lsp_batch_plan_info", "lsp_batch_run", "lsp_batch_plan_destroy",
@@ -42,7 +42,7 @@ class SplineInfo(ctypes.Structure):
                 ("D", ctypes.c_int * 3), ("shift", (ctypes.c_int * 3) * 4), ("taps", ctypes.c_int),
                 ("union_taps", ctypes.c_int), ("n_reference", ctypes.c_int),
                 ("degree", ctypes.c_int), ("radius", ctypes.c_int), ("fma_eval", ctypes.c_int),
-                ("pad", ctypes.c_int)]
+                ("pad", ctypes.c_int), ("continuity", ctypes.c_int)]
 
 
 _lock = threading.Lock()
@@ -80,6 +80,7 @@ def lib():
             "lsp_volume_set_coeffs": (ctypes.c_int, [vp, ctypes.POINTER(vp), ctypes.c_int, vp]),
             "lsp_eval": (ctypes.c_int, [vp, vp, ctypes.c_int, i64, vp, vp]),
             "lsp_eval_grad": (ctypes.c_int, [vp, vp, ctypes.c_int, i64, vp, vp, vp]),
+            "lsp_eval_hessian": (ctypes.c_int, [vp, vp, ctypes.c_int, i64, vp, vp, vp, vp]),
             "lsp_eval_binned_workspace_size": (ctypes.c_int, [vp, ctypes.c_int, i64,
                                                               ctypes.POINTER(ctypes.c_size_t)]),
             "lsp_eval_binned": (ctypes.c_int, [vp, vp, ctypes.c_int, i64, vp, vp, vp, ctypes.c_size_t,

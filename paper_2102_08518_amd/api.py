@@ -75,6 +75,11 @@ class Spline:
         N.check(N.lib().lsp_spline_get_info(h, ctypes.byref(info)))
         self.info = info
 
+    @property
+    def continuity(self) -> int:
+        """phi is C^continuity (second derivatives need at least 1)."""
+        return self.info.continuity
+
     @classmethod
     def tricubic(cls):
         return cls(LATTICES["cc"], DIRECTIONS["tricubic"])
@@ -231,6 +236,20 @@ class Volume:
         N.check(N.lib().lsp_eval_grad(self._h, _ptr(pts), _TORCH_DT[pts.dtype], n, _ptr(val),
                                       _ptr(grad), _stream(pts.device)))
         return val, grad
+
+    def eval_hessian(self, pts: torch.Tensor, want_value: bool = True, want_grad: bool = True):
+        """(f or None, grad (N, 3) or None, Hessian (N, 3, 3)) at the points.
+        Only for splines that are at least C^1 (Spline.continuity >= 1)."""
+        pts = self._pts(pts)
+        n = pts.shape[0]
+        dev = pts.device
+        val = torch.empty(n, dtype=torch.float32, device=dev) if want_value else None
+        grad = torch.empty(n, 3, dtype=torch.float32, device=dev) if want_grad else None
+        h6 = torch.empty(n, 6, dtype=torch.float32, device=dev)
+        N.check(N.lib().lsp_eval_hessian(self._h, _ptr(pts), _TORCH_DT[pts.dtype], n, _ptr(val),
+                                         _ptr(grad), _ptr(h6), _stream(dev)))
+        idx = torch.tensor([0, 1, 2, 1, 3, 4, 2, 4, 5], device=dev)
+        return val, grad, h6[:, idx].reshape(n, 3, 3)
 
     def workspace_bytes(self, n: int) -> int:
         b = ctypes.c_size_t()

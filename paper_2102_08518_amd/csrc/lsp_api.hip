@@ -85,7 +85,46 @@ struct SplineDef {
     int shift[4][3];
     int taps, union_taps, n_reference, degree, radius, fma_eval, pad;
     int omin, omax;              // per-axis offset range in global axes (lattice units)
+    int continuity;              // phi in C^continuity
 };
+
+int rank3(const std::vector<std::vector<int>>& v) {
+    // rank of a set of integer 3-vectors: 3 if some triple has a nonzero
+    // determinant, else 2 if some pair has a nonzero cross product, ...
+    const size_t n = v.size();
+    for (size_t a = 0; a < n; ++a)
+        for (size_t b = a + 1; b < n; ++b)
+            for (size_t c = b + 1; c < n; ++c) {
+                const i64 d = (i64)v[a][0] * (v[b][1] * v[c][2] - v[b][2] * v[c][1]) -
+                              (i64)v[a][1] * (v[b][0] * v[c][2] - v[b][2] * v[c][0]) +
+                              (i64)v[a][2] * (v[b][0] * v[c][1] - v[b][1] * v[c][0]);
+                if (d) return 3;
+            }
+    for (size_t a = 0; a < n; ++a)
+        for (size_t b = a + 1; b < n; ++b)
+            if (v[a][1] * v[b][2] != v[a][2] * v[b][1] || v[a][0] * v[b][2] != v[a][2] * v[b][0] ||
+                v[a][0] * v[b][1] != v[a][1] * v[b][0])
+                return 2;
+    for (const auto& x : v)
+        if (x[0] || x[1] || x[2]) return 1;
+    return 0;
+}
+
+// A box spline is C^(m-2) where m is the fewest directions whose removal
+// leaves a set that does not span the space.
+int box_continuity(const std::vector<std::vector<int>>& dirs) {
+    const int n = (int)dirs.size();
+    int m = n;
+    for (unsigned mask = 1; mask < (1u << n); ++mask) {
+        const int k = __builtin_popcount(mask);
+        if (k >= m) continue;
+        std::vector<std::vector<int>> rest;
+        for (int j = 0; j < n; ++j)
+            if (!(mask >> j & 1)) rest.push_back(dirs[j]);
+        if (rank3(rest) < 3) m = k;
+    }
+    return m - 2;
+}
 
 std::vector<int> canon_dir(std::vector<int> d) {
     int sg = 0;
@@ -130,6 +169,7 @@ SplineDef make_def() {
     // an active point's taps reach at most 2 * radius lattice units outside
     // the stored range: ceil(2 radius / D) sites, plus one
     s.pad = (2 * s.radius + s.D - 1) / s.D + 1;
+    s.continuity = box_continuity(s.dirs);
     return s;
 }
 
@@ -362,6 +402,7 @@ static void fill_info(const SplineDef& d, lsp_spline_info* o) {
     o->radius = d.radius;
     o->fma_eval = d.fma_eval;
     o->pad = d.pad;
+    o->continuity = d.continuity;
 }
 
 lsp_status lsp_spline_get_info(const lsp_spline* sp, lsp_spline_info* out) {
@@ -449,7 +490,8 @@ static lsp_status check_eval_args(const lsp_volume* vol, const void* pts, lsp_dt
 }
 
 static lsp_status run_eval(const lsp_volume* vol, const void* pts, lsp_dtype pd, int64_t N,
-                           int mode, float* out, float* grad, const float* gin, hipStream_t stream) {
+                           int mode, float* out, float* grad, const float* gin, hipStream_t stream,
+                           float* hess = nullptr) {
     lsp::EvalArgs a{};
     a.kind = vol->def.kind;
     a.ctype = vol->ctype;
@@ -464,6 +506,7 @@ static lsp_status run_eval(const lsp_volume* vol, const void* pts, lsp_dtype pd,
     a.out = out;
     a.grad = grad;
     a.gin = gin;
+    a.hess = hess;
     a.stream = stream;
     a.lds_bytes = eval_lds_bytes();
     a.mfma = mfma_for(vol->ctype);
@@ -492,6 +535,17 @@ lsp_status lsp_eval_grad(const lsp_volume* vol, const void* pts, lsp_dtype pts_d
     if (st) return st;
     if (N > 0 && !grad) return fail(LSP_E_INVALID_ARG, "grad is NULL");
     return run_eval(vol, pts, pts_dtype, N, lsp::kValueGrad, val, grad, nullptr, stream);
+}
+
+lsp_status lsp_eval_hessian(const lsp_volume* vol, const void* pts, lsp_dtype pts_dtype,
+                            int64_t N, float* val, float* grad, float* hess, hipStream_t stream) {
+    lsp_status st = check_eval_args(vol, pts, pts_dtype, N);
+    if (st) return st;
+    if (vol->def.continuity < 1)
+        return fail(LSP_E_UNSUPPORTED, "%s is only C^%d: no second derivatives", vol->def.name,
+                    vol->def.continuity);
+    if (N > 0 && !hess) return fail(LSP_E_INVALID_ARG, "hess is NULL");
+    return run_eval(vol, pts, pts_dtype, N, lsp::kValueGradHess, val, grad, nullptr, stream, hess);
 }
 
 // Bin extent 2^lb coset units: the smallest lb >= LSP_BIN_LB (default 3)

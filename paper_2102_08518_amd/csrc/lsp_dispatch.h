@@ -19,7 +19,7 @@ inline int mfma_points_per_thread(int N) {
 
 template <int KIND, class CT, class PT, int MODE, bool PRED>
 hipError_t launch_one(const EvalArgs& a) {
-    if constexpr (mfma_eligible<KIND>() && MODE != kGradX && !PRED) {
+    if constexpr (mfma_eligible<KIND>() && (MODE == kValue || MODE == kValueGrad) && !PRED) {
         if (a.mfma) {
             const int ppt = mfma_points_per_thread(a.N);
             const int blocks = (a.N + kBlock * ppt - 1) / (kBlock * ppt);
@@ -32,7 +32,7 @@ hipError_t launch_one(const EvalArgs& a) {
     const int blocks = (a.N + kBlock - 1) / kBlock;
     hipLaunchKernelGGL((k_eval<KIND, CT, PT, MODE, PRED>), dim3(blocks), dim3(kBlock), a.lds_bytes, a.stream,
                        static_cast<const PT*>(a.pts), a.N, a.coef, a.nbytes, a.g, a.out, a.grad,
-                       a.gin);
+                       a.gin, a.hess);
     return hipGetLastError();
 }
 
@@ -42,6 +42,7 @@ hipError_t launch_mode(const EvalArgs& a) {
         case kValue: return launch_one<KIND, CT, PT, kValue, PRED>(a);
         case kValueGrad: return launch_one<KIND, CT, PT, kValueGrad, PRED>(a);
         case kGradX: return launch_one<KIND, CT, PT, kGradX, PRED>(a);
+        case kValueGradHess: return launch_one<KIND, CT, PT, kValueGradHess, PRED>(a);
     }
     return hipErrorInvalidValue;
 }

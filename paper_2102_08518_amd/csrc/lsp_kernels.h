@@ -70,6 +70,37 @@ __device__ __forceinline__ float poly_value_grad(const float* c, const Loc& L, f
                                                           g[1], g[2]);
 }
 
+template <int KIND, bool PREDICATED>
+__device__ __forceinline__ float poly_value_grad_hess(const float* c, const Loc& L, float* g, float* h) {
+    return PolyOf<KIND>::template value_grad_hess<PREDICATED>(c, L.y[0], L.y[1], L.y[2], L.region,
+                                                               g[0], g[1], g[2], h);
+}
+
+// Hessian back to global axes: with y = G (x - k), G a signed permutation,
+// d2f/dx_a dx_b = sgn[r] sgn[s] d2f/dy_r dy_s for axis[r] = a, axis[s] = b.
+// hr, hg: (00, 01, 02, 11, 12, 22).
+__device__ __forceinline__ float sym3(const float* hr, int i, int j) {
+    const int lo = i < j ? i : j, hi = i < j ? j : i;
+    return lo == 0 ? (hi == 0 ? hr[0] : (hi == 1 ? hr[1] : hr[2]))
+                   : (lo == 1 ? (hi == 1 ? hr[3] : hr[4]) : hr[5]);
+}
+
+__device__ __forceinline__ void hess_to_global(const Loc& L, const float* hr, float* hg) {
+    int rr[3];
+    float sg[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        rr[a] = L.axis[0] == a ? 0 : (L.axis[1] == a ? 1 : 2);
+        sg[a] = rr[a] == 0 ? L.sgn[0] : (rr[a] == 1 ? L.sgn[1] : L.sgn[2]);
+    }
+    hg[0] = sym3(hr, rr[0], rr[0]);
+    hg[1] = sg[0] * sg[1] * sym3(hr, rr[0], rr[1]);
+    hg[2] = sg[0] * sg[2] * sym3(hr, rr[0], rr[2]);
+    hg[3] = sym3(hr, rr[1], rr[1]);
+    hg[4] = sg[1] * sg[2] * sym3(hr, rr[1], rr[2]);
+    hg[5] = sym3(hr, rr[2], rr[2]);
+}
+
 // Gradient back to global axes: y = G (x - k) with G a signed permutation,
 // so df/dx = G^T df/dy, i.e. component axis[r] is sgn[r] * df/dy_r.
 __device__ __forceinline__ void grad_to_global(const Loc& L, const float* gr, float* gx) {
@@ -96,13 +127,16 @@ __device__ __forceinline__ void load_point(const PT* __restrict__ pts, int i, PT
 // MODE kValue:     out[o] = f(x_i)
 // MODE kValueGrad: out[o] = f(x_i) (if out), grad[3o..] = grad f(x_i)
 // MODE kGradX:     grad[3o..] = gin[o] * grad f(x_i)        (dL/dx)
+// MODE kValueGradHess: out[o], grad[3o..] (each if non-null), hess[6o..] =
+//                  the Hessian (xx, xy, xz, yy, yz, zz)
 // Evaluates the point x (coordinates already loaded) and writes its results
 // to output index o.
 template <int KIND, class CT, class PT, int MODE, bool PREDICATED>
 __device__ __forceinline__ void eval_at(const PT x[3], int o, const void* __restrict__ coef,
                                         unsigned nbytes, const VolGeom& g,
                                         float* __restrict__ out, float* __restrict__ grad,
-                                        const float* __restrict__ gin) {
+                                        const float* __restrict__ gin,
+                                        float* __restrict__ hess = nullptr) {
     using T = TablesOf<KIND>;
     Loc L;
     locate<KIND>(x, g, L);
@@ -113,6 +147,18 @@ __device__ __forceinline__ void eval_at(const PT x[3], int o, const void* __rest
     if (MODE == kValue) {
         const float f = poly_value<KIND, PREDICATED>(c, L);
         out[o] = L.active ? f : (L.nan ? qnan : 0.0f);
+    } else if (MODE == kValueGradHess) {
+        float gr[3], gx[3], hr[6], hx[6];
+        const float f = poly_value_grad_hess<KIND, PREDICATED>(c, L, gr, hr);
+        grad_to_global(L, gr, gx);
+        hess_to_global(L, hr, hx);
+        const float fill = L.nan ? qnan : 0.0f;
+        if (out) out[o] = L.active ? f : fill;
+        if (grad)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) grad[3 * (size_t)o + a] = L.active ? gx[a] : fill;
+#pragma unroll
+        for (int a = 0; a < 6; ++a) hess[6 * (size_t)o + a] = L.active ? hx[a] : fill;
     } else {
         float gr[3], gx[3];
         const float f = poly_value_grad<KIND, PREDICATED>(c, L, gr);
@@ -131,10 +177,11 @@ __device__ __forceinline__ void eval_point(const PT* __restrict__ pts, int i, in
                                            const void* __restrict__ coef, unsigned nbytes,
                                            const VolGeom& g, float* __restrict__ out,
                                            float* __restrict__ grad,
-                                           const float* __restrict__ gin) {
+                                           const float* __restrict__ gin,
+                                           float* __restrict__ hess = nullptr) {
     PT x[3];
     load_point(pts, i, x);
-    eval_at<KIND, CT, PT, MODE, PREDICATED>(x, o, coef, nbytes, g, out, grad, gin);
+    eval_at<KIND, CT, PT, MODE, PREDICATED>(x, o, coef, nbytes, g, out, grad, gin, hess);
 }
 
 template <int KIND, class CT, class PT, int MODE, bool PREDICATED>
@@ -142,10 +189,11 @@ __global__ __launch_bounds__(256) void k_eval(const PT* __restrict__ pts, int N,
                                               const void* __restrict__ coef, unsigned nbytes,
                                               VolGeom g, float* __restrict__ out,
                                               float* __restrict__ grad,
-                                              const float* __restrict__ gin) {
+                                              const float* __restrict__ gin,
+                                              float* __restrict__ hess) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
-    eval_point<KIND, CT, PT, MODE, PREDICATED>(pts, i, i, coef, nbytes, g, out, grad, gin);
+    eval_point<KIND, CT, PT, MODE, PREDICATED>(pts, i, i, coef, nbytes, g, out, grad, gin, hess);
 }
 
 }  // namespace lsp

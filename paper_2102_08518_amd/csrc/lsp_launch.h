@@ -9,7 +9,7 @@
 namespace lsp {
 
 enum CoefType : int { kCF32 = 0, kCBF16 = 1, kCF16 = 2 };
-enum Mode : int { kValue = 0, kValueGrad = 1, kGradX = 2 };
+enum Mode : int { kValue = 0, kValueGrad = 1, kGradX = 2, kValueGradHess = 3 };
 
 struct EvalArgs {
     int kind;           // Kind
@@ -24,6 +24,7 @@ struct EvalArgs {
     VolGeom g;
     float* out;
     float* grad;
+    float* hess;        // kValueGradHess: N x 6 (xx, xy, xz, yy, yz, zz)
     const float* gin;
     hipStream_t stream;
     unsigned lds_bytes;  // dynamic LDS per workgroup (occupancy control), usually 0

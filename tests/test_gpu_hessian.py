@@ -1,0 +1,191 @@
+"""GPU parity of the value + gradient + Hessian kernel (lsp_eval_hessian)
+against the FP64 CPU checker's second derivatives (the derivative identity
+of box splines applied twice), plus finite differences of the GPU gradient,
+exactness on quadratic data and the edge cases.
+
+Tolerance: |H_gpu - H_ref| <= 4e-6 max|c| per entry, twice the gradient's
+bound per derivative taken: the second-derivative polynomials of the
+reference sub-region have coefficients a few times those of the gradient
+polynomials and are evaluated in FP32 the same way (measured: about 3e-7).
+
+For the C^1 splines (fcc6, triquadratic) the second partials jump across
+sub-region boundaries; a point that rounds onto the other side of a boundary
+than the checker's FP64 assignment is accepted when the checker's Hessian at
+a point a distance 1e-4 away agrees with the GPU's."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2102_08518_amd import api, inputs
+
+pytestmark = pytest.mark.gpu
+
+ORC = {"tricubic": oracle.TRICUBIC, "bcc8": oracle.BCC8, "fcc6": oracle.FCC6,
+       "triquadratic": oracle.TRIQUADRATIC}
+SMOOTH = list(ORC)
+C0 = ["trilinear", "bcc4"]
+TORCH_DT = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}
+TOL = 4e-6
+
+
+def _stored(c, storage):
+    return torch.tensor(c, dtype=torch.float32).to(TORCH_DT[storage]).to(torch.float64).numpy()
+
+
+def _mk(name, E, c, storage, dev):
+    vol = api.Volume(api.Spline.named(name), (E, E, E), storage)
+    vol.set(torch.tensor(c, dtype=torch.float32, device=dev))
+    return vol
+
+
+def _points(name, E, n, rng, outside=True):
+    lat = inputs.LATTICE[name]
+    hi = lat["D"] * (E - 1) + 1
+    x = rng.uniform(-4, hi + 4, (n, 3)) if outside else rng.uniform(*inputs.interior(name, E), (n, 3))
+    return x.astype(np.float32)
+
+
+def _check_hessian(name, E, cs, x, H, tol):
+    """Entrywise comparison with the checker, with the boundary allowance for
+    the C^1 splines."""
+    _, _, ref = oracle.evaluate_hessian(ORC[name], (E, E, E), list(cs), x)
+    err = np.abs(H - ref).reshape(len(x), -1).max(axis=1)
+    bad = np.nonzero(err > tol)[0]
+    if len(bad) and name in ("fcc6", "triquadratic"):
+        rng = np.random.default_rng(5)
+        still = []
+        for i in bad:
+            u = rng.normal(size=(16, 3))
+            u *= 1e-4 / np.linalg.norm(u, axis=1, keepdims=True)
+            _, _, near = oracle.evaluate_hessian(ORC[name], (E, E, E), list(cs), x[i] + u)
+            if np.abs(near - H[i]).reshape(16, -1).max(axis=1).min() > tol + 1e-3 * np.abs(cs).max():
+                still.append(i)
+        assert len(bad) <= max(2, len(x) // 500), (len(bad), err.max())
+        bad = np.array(still, dtype=np.int64)
+    assert len(bad) == 0, (name, len(bad), err.max(), x[bad[:3]])
+    return float(err.max())
+
+
+@pytest.mark.parametrize("name", SMOOTH)
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_hessian_matches_oracle(device, name, storage):
+    print("case hessian", name, storage, flush=True)
+    rng = np.random.default_rng(300 + len(name) + len(storage))
+    E = 10
+    nc = ORC[name].n_cosets
+    c = rng.uniform(-1, 1, (nc, E, E, E))
+    x = _points(name, E, 3001, rng)
+    vol = _mk(name, E, c, storage, device)
+    val, grad, H = vol.eval_hessian(torch.tensor(x, device=device))
+    cs = _stored(c, storage)
+    xs = x.astype(np.float64)
+    fref, gref = oracle.evaluate(ORC[name], (E, E, E), list(cs), xs, grad=True)
+    assert np.abs(val.cpu().numpy() - fref).max() <= 2e-6
+    assert np.abs(grad.cpu().numpy() - gref).max() <= 2e-5
+    H = H.cpu().numpy().astype(np.float64)
+    assert np.array_equal(H, H.transpose(0, 2, 1))
+    err = _check_hessian(name, E, cs, xs, H, TOL * np.abs(cs).max())
+    print("  max |H - H_ref| =", err, flush=True)
+
+
+@pytest.mark.parametrize("name", SMOOTH)
+def test_hessian_outputs_agree_with_eval_grad(device, name):
+    """The value and gradient written by the Hessian kernel are bit-identical
+    to lsp_eval_grad's when both are computed by the same polynomials, and the
+    optional outputs may be skipped; F64 points take the same path."""
+    print("case hessian-consistency", name, flush=True)
+    rng = np.random.default_rng(11)
+    E = 9
+    nc = ORC[name].n_cosets
+    c = rng.uniform(-1, 1, (nc, E, E, E))
+    x = _points(name, E, 1537, rng).astype(np.float64) + rng.uniform(-1e-3, 1e-3, (1537, 3))
+    vol = _mk(name, E, c, "f32", device)
+    xt = torch.tensor(x, device=device)
+    v1, g1, H1 = vol.eval_hessian(xt)
+    _, _, H2 = vol.eval_hessian(xt, want_value=False, want_grad=False)
+    assert torch.equal(H1, H2)
+    v0, g0 = vol.eval_grad(xt)
+    assert torch.allclose(v1, v0, rtol=0, atol=2e-6)
+    assert torch.allclose(g1, g0, rtol=0, atol=2e-5)
+    cs = _stored(c, "f32")
+    _check_hessian(name, E, cs, x, H1.cpu().numpy().astype(np.float64), TOL * np.abs(cs).max())
+
+
+@pytest.mark.parametrize("name", ["tricubic", "bcc8"])
+def test_hessian_matches_gradient_differences(device, name):
+    """For the C^2 splines the Hessian is the derivative of the GPU gradient:
+    central differences with FP64 points, step 1e-3."""
+    print("case hessian-fd", name, flush=True)
+    rng = np.random.default_rng(12)
+    E = 12
+    nc = ORC[name].n_cosets
+    c = rng.uniform(-1, 1, (nc, E, E, E)).astype(np.float32)
+    x = rng.uniform(*inputs.interior(name, E), (2000, 3))
+    vol = _mk(name, E, c, "f32", device)
+    xt = torch.tensor(x, device=device)
+    _, _, H = vol.eval_hessian(xt)
+    h = 1e-3
+    fd = torch.zeros_like(H)
+    for a in range(3):
+        e = torch.zeros(3, dtype=torch.float64, device=device)
+        e[a] = h
+        gp = vol.eval_grad(xt + e)[1]
+        gm = vol.eval_grad(xt - e)[1]
+        fd[:, :, a] = (gp - gm) / (2 * h)
+    # worst case: FP32 gradient error (<= 2e-5) / h, plus h times the jump of
+    # the third derivative where a sub-region boundary lies within h; a sign
+    # or axis mistake in the Hessian would be O(1)
+    d = (H - fd).abs().reshape(len(x), -1).max(dim=1).values
+    assert d.max().item() <= 2e-2 and d.median().item() <= 1e-3, (d.max().item(), d.median().item())
+
+
+@pytest.mark.parametrize("name", SMOOTH)
+def test_hessian_exact_on_quadratic_data(device, name):
+    """Coefficients sampled from a quadratic q: the spline reproduces q up to
+    a constant, so the Hessian is 2Q everywhere in the interior."""
+    print("case hessian-quadratic", name, flush=True)
+    E = 10
+    pos = inputs.site_positions(name, E).astype(np.float64)
+    Q = np.array([[0.3, -0.1, 0.05], [-0.1, -0.2, 0.15], [0.05, 0.15, 0.4]]) / 10
+    b = np.array([0.2, -0.3, 0.1])
+    c = np.einsum("...i,ij,...j->...", pos, Q, pos) + pos @ b + 1.0
+    rng = np.random.default_rng(13)
+    x = rng.uniform(*inputs.interior(name, E), (1000, 3)).astype(np.float32)
+    vol = _mk(name, E, c, "f32", device)
+    _, _, H = vol.eval_hessian(torch.tensor(x, device=device))
+    err = np.abs(H.cpu().numpy() - 2 * Q).max()
+    assert err <= TOL * np.abs(c).max(), err
+
+
+@pytest.mark.parametrize("name", SMOOTH)
+def test_hessian_edge_inputs(device, name):
+    """Empty input, NaN (-> NaN everywhere), infinities and far points
+    (-> 0), a ragged count with a partial last block."""
+    print("case hessian-edges", name, flush=True)
+    E = 6
+    nc = ORC[name].n_cosets
+    c = np.random.default_rng(14).uniform(-1, 1, (nc, E, E, E))
+    vol = _mk(name, E, c, "f32", device)
+    v, g, H = vol.eval_hessian(torch.empty(0, 3, device=device))
+    assert H.shape == (0, 3, 3)
+    inf = float("inf")
+    x = torch.tensor([[float("nan"), 1.0, 1.0], [1.0, 1.0, float("nan")], [inf, 2.0, 2.0],
+                      [-inf, 2.0, 2.0], [1e30, -1e30, 3.0], [-50.0, 3.0, 3.0], [3.0, 3.0, 3.0]],
+                     device=device)
+    v, g, H = vol.eval_hessian(x)
+    H = H.cpu()
+    assert torch.isnan(H[:2]).all() and torch.isnan(v[:2].cpu()).all() and torch.isnan(g[:2].cpu()).all()
+    assert (H[2:6] == 0).all() and (v[2:6].cpu() == 0).all() and (g[2:6].cpu() == 0).all()
+    _check_hessian(name, E, _stored(c, "f32"), x[6:].cpu().numpy().astype(np.float64),
+                   H[6:].numpy().astype(np.float64), TOL * np.abs(c).max())
+
+
+@pytest.mark.parametrize("name", C0)
+def test_hessian_refused_for_c0_splines(device, name):
+    print("case hessian-c0", name, flush=True)
+    sp = api.Spline.named(name)
+    assert sp.continuity == 0
+    vol = api.Volume(sp, (6, 6, 6), "f32")
+    with pytest.raises(RuntimeError, match="LSP_E_UNSUPPORTED"):
+        vol.eval_hessian(torch.full((4, 3), 2.5, device=device))

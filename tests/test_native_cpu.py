@@ -30,13 +30,16 @@ def test_library_exports_every_declared_symbol():
         assert lib.lsp_status_string(st)
 
 
-@pytest.mark.parametrize("name,kind,cosets,taps,union", [
-    ("tricubic", 0, 1, 64, 64), ("bcc8", 1, 2, 32, 32), ("fcc6", 2, 4, 16, 19),
-    ("trilinear", 3, 1, 8, 8), ("bcc4", 4, 2, 4, 4), ("triquadratic", 5, 1, 27, 27)])
-def test_spline_recognition(name, kind, cosets, taps, union):
+# continuity: cubic B-spline C^2, quintic BCC 8-direction box spline C^2,
+# FCC 6-direction box spline C^1, quadratic B-spline C^1, linear ones C^0
+@pytest.mark.parametrize("name,kind,cosets,taps,union,cont", [
+    ("tricubic", 0, 1, 64, 64, 2), ("bcc8", 1, 2, 32, 32, 2), ("fcc6", 2, 4, 16, 19, 1),
+    ("trilinear", 3, 1, 8, 8, 0), ("bcc4", 4, 2, 4, 4, 0), ("triquadratic", 5, 1, 27, 27, 1)])
+def test_spline_recognition(name, kind, cosets, taps, union, cont):
     sp = getattr(api.Spline, name)()
     assert sp.info.kind == kind and sp.info.n_cosets == cosets
     assert sp.info.taps == taps and sp.info.union_taps == union
+    assert sp.continuity == cont
     # another basis of the same lattice, directions shuffled and negated
     L = api.LATTICES[api.LATTICE_OF[name]]
     U = np.array([[1, 1, 0], [0, 1, 0], [0, 0, 1]], dtype=np.int32)  # unimodular
