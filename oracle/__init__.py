@@ -123,7 +123,16 @@ TRIQUADRATIC = Spline("triquadratic", np.eye(3),
                       _cols(*([(1, 0, 0)] * 3 + [(0, 1, 0)] * 3 + [(0, 0, 1)] * 3)),
                       D=(1, 1, 1), shifts=[(0, 0, 0)])
 
-SPLINES = {sp.name: sp for sp in (TRICUBIC, BCC8, BCC4, FCC6, ZP, TRILINEAR, TRIQUADRATIC)}
+# Fourth-order splines of the paper's third comparison (Sec. 5.1): the
+# seven-direction box spline on Z^3 (the axes and the four diagonals) and the
+# quartic box spline on BCC (the four diagonals and the three shortest
+# axis-aligned lattice vectors 2 e_i).
+CC7 = Spline("cc7", np.eye(3), _cols((1, 0, 0), (0, 1, 0), (0, 0, 1), *_DIAG),
+             D=(1, 1, 1), shifts=[(0, 0, 0)])
+BCC7 = Spline("bcc7", _BCC_L, _cols(*_DIAG, (2, 0, 0), (0, 2, 0), (0, 0, 2)),
+              D=(2, 2, 2), shifts=[(0, 0, 0), (1, 1, 1)])
+
+SPLINES = {sp.name: sp for sp in (TRICUBIC, BCC8, BCC4, FCC6, ZP, TRILINEAR, TRIQUADRATIC, CC7, BCC7)}
 
 
 # ---------------------------------------------------------------- calls

@@ -34,6 +34,10 @@
  * Face ties of the parallelepipeds are resolved by a fixed generic direction v
  * (a face point is inside iff z + eps*v is inside for small eps > 0), which
  * makes every level of the recurrence the v-directional limit of itself.
+ * That needs every term to see a face that several parallelepipeds share in
+ * the same way: z is rounded once to the grid 2^-48 Z^s (a move of at most
+ * 2^-49 per coordinate) and the side tests are done exactly, in integers, as
+ * adj(B) w against 0 and det(B).
  *
  * Gradients use the directional-derivative identity
  *   D_xi M_Xi(z) = M_{Xi\xi}(z) - M_{Xi\xi}(z - xi)
@@ -50,7 +54,8 @@
  * n = D * (i, j, k) + l_m, i in [0, dims[0]), ..., in C order [k][j][i]
  * (i fastest).  Sites outside the stored range contribute zero.
  *
- * Limits: s in {2, 3}; at most 8 distinct directions, multiplicity <= 15.
+ * Limits: s in {2, 3}; at most 8 distinct directions, multiplicity <= 15,
+ * direction entries in [-2, 2], support inside |z_i| < 16.
  */
 #include <math.h>
 #include <stdint.h>
@@ -62,6 +67,8 @@
 #endif
 
 #define ORC_MAXD 8   /* distinct directions */
+#define ORC_QBITS 48 /* arguments of M are rounded to the grid 2^-ORC_QBITS */
+#define ORC_ZMAX 16.0 /* every support lies in |z_i| < ORC_ZMAX (checked at set-up) */
 #define ORC_MAXC 8   /* cosets */
 #define MEMO_BITS 12
 #define MEMO_SIZE (1u << MEMO_BITS)
@@ -183,22 +190,52 @@ static double box_M(const orc_spline *sp, const int *mult, const int *shift,
 
     if (n == s) {
         /* Square basis: the normalised indicator of B[0,1)^s. */
-        double B[3][3], u[3], uv[3];
+        double B[3][3];
         int c = 0;
         for (int d = 0; d < sp->nd; ++d)
             if (mult[d]) {
                 for (int i = 0; i < s; ++i) B[i][c] = sp->dir[d][i];
                 ++c;
             }
-        if (!solve(s, B, w, u)) return 0.0;
-        solve(s, B, sp->v, uv);
+        /* u = B^-1 w = adj(B) w / det(B) with w on the grid 2^-48 Z^s:
+         * |w| < 2 ORC_ZMAX = 2^5 makes w 2^48 an exact 53-bit integer and,
+         * with |adj(B)| <= 8, the numerators exact in 64 bits, so u in
+         * (0,1), u == 0 and u == 1 are decided exactly; a tie takes the
+         * side of v. */
+        int64_t Bi[3][3], adj[3][3], wq[3];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) Bi[i][j] = (i < s && j < s) ? (int64_t)B[i][j] : (i == j);
+        for (int i = 0; i < s; ++i) wq[i] = (int64_t)ldexp(w[i], ORC_QBITS);
+        if (s == 2) {
+            adj[0][0] = Bi[1][1]; adj[0][1] = -Bi[0][1];
+            adj[1][0] = -Bi[1][0]; adj[1][1] = Bi[0][0];
+        } else {
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) {
+                    const int r0 = (j + 1) % 3, r1 = (j + 2) % 3, c0 = (i + 1) % 3, c1 = (i + 2) % 3;
+                    adj[i][j] = Bi[r0][c0] * Bi[r1][c1] - Bi[r0][c1] * Bi[r1][c0];
+                }
+        }
+        int64_t det = 0;
+        for (int j = 0; j < s; ++j) det += Bi[0][j] * adj[j][0];
+        if (det == 0) return 0.0;
+        const int64_t sg = det > 0 ? 1 : -1;
+        const int64_t one = sg * det * ((int64_t)1 << ORC_QBITS);
         for (int i = 0; i < s; ++i) {
-            if (u[i] > 0.0 && u[i] < 1.0) continue;
-            if (u[i] == 0.0 && uv[i] > 0.0) continue;
-            if (u[i] == 1.0 && uv[i] < 0.0) continue;
+            int64_t num = 0;
+            double nv = 0.0;
+            for (int j = 0; j < s; ++j) {
+                num += adj[i][j] * wq[j];
+                nv += (double)adj[i][j] * sp->v[j];
+            }
+            num *= sg;
+            nv *= (double)sg;
+            if (num > 0 && num < one) continue;
+            if (num == 0 && nv > 0.0) continue;
+            if (num == one && nv < 0.0) continue;
             return 0.0;
         }
-        return 1.0 / fabs(detn(s, B));
+        return 1.0 / (double)(sg * det);
     }
 
     uint64_t key = memo_key(sp, mult, shift);
@@ -230,12 +267,28 @@ static double box_M(const orc_spline *sp, const int *mult, const int *shift,
     return val;
 }
 
+/* z = y + centre rounded to the grid 2^-ORC_QBITS Z^s; 0 if some |z_i| is
+ * so large that z is outside the support of every spline handled here. */
+static int grid_arg(const orc_spline *sp, const double *y, double z[3]) {
+    for (int i = 0; i < 3; ++i) z[i] = 0.0;
+    for (int i = 0; i < sp->s; ++i) {
+        const double v = y[i] + sp->centre[i];
+        if (!(fabs(v) < ORC_ZMAX)) return 0;
+        z[i] = ldexp(nearbyint(ldexp(v, ORC_QBITS)), -ORC_QBITS);
+    }
+    return 1;
+}
+
 /* phi(y) and optionally its gradient. */
 static double phi_eval(const orc_spline *sp, const double *y, double *grad, memo_t *memo) {
     const int s = sp->s;
     double z[3] = {0, 0, 0};
     int zero[3] = {0, 0, 0};
-    for (int i = 0; i < s; ++i) z[i] = y[i] + sp->centre[i];
+    if (!grid_arg(sp, y, z)) {
+        if (grad)
+            for (int i = 0; i < s; ++i) grad[i] = 0.0;
+        return 0.0;
+    }
     memo->gen++;
     if (memo->gen == 0) { memset(memo->tab, 0, sizeof(memo_entry) * MEMO_SIZE); memo->gen = 1; }
     double val = sp->detL * box_M(sp, sp->mult0, zero, z, memo);
@@ -335,7 +388,10 @@ static int phi_hess(const orc_spline *sp, const double *y, double *val, double *
     *val = phi_eval(sp, y, grad, memo);
     double z[3] = {0, 0, 0};
     int zero[3] = {0, 0, 0};
-    for (int i = 0; i < s; ++i) z[i] = y[i] + sp->centre[i];
+    if (!grid_arg(sp, y, z)) {
+        for (int i = 0; i < s * s; ++i) hess[i] = 0.0;
+        return 1;
+    }
     int dirs[3];
     double A[3][3], R[3][3];
     if (pick_dirs(sp, sp->mult0, dirs, A) != s) return 0;
@@ -402,7 +458,14 @@ static int spline_init(orc_spline *sp, int s, int n, const int *Xi, const int *L
         }
         sp->centre[i] = c;
         sp->halfwidth[i] = h;
+        /* the uncentred support spans [c - h, c + h]; the exact face tests
+         * need it inside |z| < ORC_ZMAX, and |adj(B)| <= 8 needs small
+         * direction entries */
+        if (fabs(c) + h >= ORC_ZMAX) return -6;
     }
+    for (int d = 0; d < sp->nd; ++d)
+        for (int i = 0; i < s; ++i)
+            if (abs(sp->dir[d][i]) > 2) return -6;
     double Lm[3][3];
     for (int i = 0; i < s; ++i)
         for (int j = 0; j < s; ++j) Lm[i][j] = L[i * s + j];

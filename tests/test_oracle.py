@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import oracle
-from oracle import BCC4, BCC8, FCC6, TRICUBIC, TRILINEAR, TRIQUADRATIC, ZP
+from oracle import BCC4, BCC7, BCC8, CC7, FCC6, TRICUBIC, TRILINEAR, TRIQUADRATIC, ZP
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 rng = np.random.default_rng(20210208)
@@ -135,16 +135,20 @@ def _support_count(sp, x, radius):
             sites.append(n)
     sites = np.array(sites)
     v = np.abs(oracle.phi(sp, x - sites))
-    if np.any((v > 1e-16) & (v < 1e-9)):
+    if np.any((v > 0) & (v < 1e-9)):
         return None  # too close to the support boundary to count reliably
     return int((v > 1e-9).sum())
 
 
 @pytest.mark.parametrize("sp,count", [(BCC4, 4), (ZP, 7), (TRICUBIC, 64), (TRILINEAR, 8),
-                                      (BCC8, 32), (FCC6, 16), (TRIQUADRATIC, 27)])
+                                      (BCC8, 32), (FCC6, 16), (TRIQUADRATIC, 27), (CC7, 53),
+                                      (BCC7, 30)])
 def test_taps_at_generic_points(sp, count):
     """BCC linear: four lookups (Sec. 5.1); ZP: seven sites c0..c6 (Fig. 1);
-    tricubic: 64 fetches (Sec. 5.1); in general vol(supp)/|det L|."""
+    tricubic: 64 fetches (Sec. 5.1); in general vol(supp)/|det L|, the
+    support being the zonotope of Xi, whose volume is the sum of |det| over
+    all triples of directions (CC7: 1 + 12 + 24 + 16 = 53; BCC7:
+    (8 + 48 + 48 + 16) / 4 = 30)."""
     done = 0
     while done < 5:
         x = rng.uniform(-3, 3, sp.s)
@@ -163,7 +167,7 @@ def test_bcc_linear_interpolates():
 
 # ---------------------------------------------------------- invariants
 
-SPL3 = [TRICUBIC, BCC8, FCC6]
+SPL3 = [TRICUBIC, BCC8, FCC6, CC7, BCC7]
 
 
 def _lattice_box(sp, E):
@@ -171,15 +175,23 @@ def _lattice_box(sp, E):
     return dims
 
 
+def _ext(sp, E):
+    """E, or the smallest extent whose interior box (below) is at least one
+    lattice unit wide."""
+    need = int(np.ceil((2 * sp.halfwidth.max() + 3) / sp.D.min())) + 1
+    return max(E, need)
+
+
 def _interior(sp, E, n):
     hw = sp.halfwidth.max()
     hi = (E - 1) * sp.D.min() + sp.shifts.min()
+    assert hi - hw - 1 >= hw + 2, "extent too small for an interior box"
     return rng.uniform(hw + 1, hi - hw - 1, (n, sp.s))
 
 
 @pytest.mark.parametrize("sp", SPL3 + [ZP, BCC4, TRILINEAR, TRIQUADRATIC])
 def test_partition_of_unity_and_linear_reproduction(sp):
-    E = 12 if sp.D.max() == 1 else 8
+    E = _ext(sp, 12 if sp.D.max() == 1 else 8)
     dims = _lattice_box(sp, E)
     x = _interior(sp, E, 60)
     pos = oracle.site_positions(sp, dims).astype(np.float64)
@@ -195,11 +207,12 @@ def test_partition_of_unity_and_linear_reproduction(sp):
 
 @pytest.mark.parametrize("sp,M", [(TRICUBIC, np.eye(3) / 3), (BCC8, 2 * np.eye(3) / 3),
                                   (FCC6, np.eye(3) / 3), (ZP, np.eye(2) / 4),
-                                  (TRIQUADRATIC, np.eye(3) / 4)])
+                                  (TRIQUADRATIC, np.eye(3) / 4), (CC7, 5 * np.eye(3) / 12),
+                                  (BCC7, 2 * np.eye(3) / 3)])
 def test_second_moment_is_XiXiT_over_12(sp, M):
     """Sum_n (n-x)(n-x)^T phi(x-n) = Xi Xi^T / 12 for approximation order >= 3."""
     np.testing.assert_allclose(sp.Xi @ sp.Xi.T / 12.0, M)
-    E = 12 if sp.D.max() == 1 else 8
+    E = _ext(sp, 12 if sp.D.max() == 1 else 8)
     dims = _lattice_box(sp, E)
     x = _interior(sp, E, 40)
     pos = oracle.site_positions(sp, dims).astype(np.float64)
@@ -214,11 +227,11 @@ def test_second_moment_is_XiXiT_over_12(sp, M):
             np.testing.assert_allclose(f, u[:, a] * u[:, b] + M[a, b], atol=1e-11)
 
 
-@pytest.mark.parametrize("sp", [TRICUBIC, BCC8])
+@pytest.mark.parametrize("sp", [TRICUBIC, BCC8, CC7, BCC7])
 def test_cubic_reproduction_order4(sp):
     """Approximation order 4: cubic data give u_a u_b u_c + u_a M_bc + u_b M_ac + u_c M_ab."""
     M = sp.Xi @ sp.Xi.T / 12.0
-    E = 10 if sp.D.max() == 1 else 7
+    E = _ext(sp, 10 if sp.D.max() == 1 else 7)
     dims = _lattice_box(sp, E)
     x = _interior(sp, E, 30)
     pos = oracle.site_positions(sp, dims).astype(np.float64)
@@ -276,12 +289,20 @@ def test_integral_is_det_L(sp):
         assert abs(integral - sp.det_L) < 1e-12
 
 
-@pytest.mark.parametrize("sp,order", [(TRICUBIC, 2), (BCC8, 2), (FCC6, 1), (ZP, 1)])
+@pytest.mark.parametrize("sp,order", [(TRICUBIC, 2), (BCC8, 2), (FCC6, 1), (ZP, 1), (CC7, 2),
+                                      (BCC7, 2)])
 def test_smoothness_across_knot_planes(sp, order):
-    """phi is C^{m-2}: values (and gradients for C^1) continue across knot planes."""
+    """phi is C^{m-2}: values (and gradients for C^1, Hessians for C^2)
+    continue across knot planes."""
     eps = 1e-7
     pts = rng.uniform(-1.5, 1.5, (200, sp.s))
-    if sp is TRICUBIC:
+    if sp is CC7:
+        pts[:, 1] = 1 - pts[:, 0]  # x + y = 1 plane
+        nrm = np.array([1.0, 1.0, 0]) / np.sqrt(2)
+    elif sp is BCC7:
+        pts[:, 2] = np.round(pts[:, 2])  # z in Z
+        nrm = np.array([0, 0, 1.0])
+    elif sp is TRICUBIC:
         pts[:, 0] = np.round(pts[:, 0])
         nrm = np.array([1.0, 0, 0])
     elif sp is BCC8:
@@ -298,13 +319,37 @@ def test_smoothness_across_knot_planes(sp, order):
     assert np.abs(a - b).max() < 1e-6
     if order >= 1:
         assert np.abs(ga - gb).max() < 1e-5
+    if order >= 2:
+        # f = phi(x - n0) from a single unit coefficient, away from the edges
+        E = _ext(sp, 9)
+        n0 = np.full(3, 4 * sp.D[0])
+        coeffs = [np.zeros((E, E, E)) for _ in range(sp.n_cosets)]
+        coeffs[0][4, 4, 4] = 1.0
+        _, _, Ha = oracle.evaluate_hessian(sp, (E,) * 3, coeffs, n0 + pts + 1e-6 * nrm)
+        _, _, Hb = oracle.evaluate_hessian(sp, (E,) * 3, coeffs, n0 + pts - 1e-6 * nrm)
+        assert np.abs(Ha - Hb).max() < 1e-4
+
+
+@pytest.mark.parametrize("sp", SPL3 + [BCC4, TRILINEAR, TRIQUADRATIC])
+def test_continuous_where_knot_planes_meet(sp):
+    """Every spline here is at least C^0, so phi on edges and vertices of the
+    knot-plane arrangement (two or three coordinates on half-integers, where
+    faces of the recurrence's parallelepipeds coincide) equals phi a
+    distance 1e-9 away."""
+    y = rng.uniform(-2.5, 2.5, (300, 3))
+    for k in range(300):
+        cols = rng.choice(3, size=2 + k % 2, replace=False)
+        y[k, cols] = np.round(2 * y[k, cols]) / 2
+    d = rng.normal(size=y.shape)
+    d *= 1e-9 / np.linalg.norm(d, axis=1, keepdims=True)
+    np.testing.assert_allclose(oracle.phi(sp, y), oracle.phi(sp, y + d), atol=1e-7)
 
 
 # ------------------------------------------------------ enumeration, grads
 
 @pytest.mark.parametrize("sp", SPL3 + [ZP])
 def test_pruned_equals_brute_force(sp):
-    E = 6 if sp.D.max() > 1 else 9
+    E = _ext(sp, 6 if sp.D.max() > 1 else 9)
     dims = (E,) * sp.s
     coeffs = [rng.uniform(-1, 1, tuple(dims[::-1])) for _ in range(sp.n_cosets)]
     hi = (E - 1) * sp.D.max() + 1
@@ -316,7 +361,7 @@ def test_pruned_equals_brute_force(sp):
 
 @pytest.mark.parametrize("sp", SPL3)
 def test_gradient_matches_central_differences(sp):
-    E = 8
+    E = _ext(sp, 8)
     dims = (E,) * 3
     coeffs = [rng.uniform(-1, 1, (E, E, E)) for _ in range(sp.n_cosets)]
     x = _interior(sp, E, 20)
@@ -332,7 +377,7 @@ def test_gradient_matches_central_differences(sp):
 
 @pytest.mark.parametrize("sp", SPL3)
 def test_gradient_exact_for_affine_data(sp):
-    E = 8
+    E = _ext(sp, 8)
     dims = (E,) * 3
     pos = oracle.site_positions(sp, dims).astype(np.float64)
     a = np.array([0.3, -1.1, 0.45])
@@ -345,7 +390,7 @@ def test_gradient_exact_for_affine_data(sp):
 @pytest.mark.parametrize("sp", SPL3)
 def test_backward_coef_fd_and_moments(sp):
     """MSE loss is quadratic in c, so central differences in c are exact."""
-    E = 7
+    E = _ext(sp, 7)
     dims = (E,) * 3
     coeffs = [rng.uniform(-1, 1, (E, E, E)) for _ in range(sp.n_cosets)]
     x = _interior(sp, E, 60)
@@ -378,7 +423,7 @@ def test_backward_coef_fd_and_moments(sp):
 
 def test_backward_x_is_g_times_grad():
     sp = BCC8
-    E = 7
+    E = _ext(sp, 7)
     dims = (E,) * 3
     coeffs = [rng.uniform(-1, 1, (E, E, E)) for _ in range(2)]
     x = _interior(sp, E, 10)
@@ -390,7 +435,7 @@ def test_backward_x_is_g_times_grad():
 
 # ------------------------------------------------------------ Hessians
 
-HESS = [TRICUBIC, BCC8, FCC6, TRIQUADRATIC]   # C^1 and smoother after removing a direction
+HESS = [TRICUBIC, BCC8, FCC6, TRIQUADRATIC, CC7, BCC7]   # C^1 and smoother after removing a direction
 
 
 def test_tricubic_hessian_closed_form():
@@ -427,7 +472,7 @@ def test_tricubic_hessian_closed_form():
 
 @pytest.mark.parametrize("sp", HESS)
 def test_hessian_symmetric_and_matches_gradient_differences(sp):
-    E = 8
+    E = _ext(sp, 8)
     dims = (E,) * 3
     coeffs = [rng.uniform(-1, 1, (E, E, E)) for _ in range(sp.n_cosets)]
     x = _interior(sp, E, 20)
@@ -451,7 +496,7 @@ def test_hessian_exact_for_quadratic_data(sp):
     """c_n = n^T Q n + b.n + a gives f = q(x) + const for these splines
     (quadratics are reproduced up to the second-moment constant), so the
     Hessian is exactly 2Q."""
-    E = 10
+    E = _ext(sp, 10)
     dims = (E,) * 3
     pos = oracle.site_positions(sp, dims).astype(np.float64)
     Q = np.array([[0.3, -0.1, 0.05], [-0.1, -0.2, 0.15], [0.05, 0.15, 0.4]])
