@@ -77,7 +77,8 @@ typedef struct lsp_volume lsp_volume;  /* opaque: a spline plus bound coefficien
 typedef struct lsp_spline_info {
     int s;                 /* dimension (3) */
     int kind;              /* 0 tricubic on Z^3, 1 BCC 8-direction, 2 FCC 6-direction,
-                              3 trilinear, 4 BCC linear (4-direction), 5 triquadratic */
+                              3 trilinear, 4 BCC linear (4-direction), 5 triquadratic,
+                              6 Z^3 7-direction, 7 BCC quartic (7-direction) */
     int n_cosets;          /* Cartesian cosets of the lattice */
     int D[3];              /* coset scale */
     int shift[4][3];       /* coset shifts (first n_cosets rows used) */
@@ -128,9 +129,12 @@ lsp_status lsp_set_option(int option, int value);
  *   Xi      host, s*n_dirs int32, row-major; the COLUMNS are the directions.
  *           Direction order and signs do not matter (phi is centred).
  *   out     receives a handle owned by the caller (lsp_spline_destroy).
- * Supported pairs: Z^3 with Xi = [I I I I] (tricubic B-spline); the BCC
- * lattice with its four diagonals each taken twice; the FCC lattice with the
- * six directions (1,+-1,0), (1,0,+-1), (0,1,+-1).  Anything else returns
+ * Supported pairs (the box splines of Sec. 5.1's comparisons): Z^3 with
+ * Xi = [I I] (trilinear), [I I I] (triquadratic), [I I I I] (tricubic) and
+ * [I, the four diagonals (+-1,+-1,+-1)] (7-direction, fourth order); the BCC
+ * lattice with its four diagonals once (linear), twice (8-direction) or with
+ * 2I (quartic, 7-direction); the FCC lattice with the six directions
+ * (1,+-1,0), (1,0,+-1), (0,1,+-1).  Anything else returns
  * LSP_E_UNSUPPORTED.  Host only; touches no device.
  */
 lsp_status lsp_spline_create(int s, const int32_t* L, const int32_t* Xi, int n_dirs,

@@ -34,9 +34,11 @@ DIRECTIONS = {
     "trilinear": np.concatenate([_E3] * 2, axis=1),
     "bcc4": _DIAG.T.copy(),
     "triquadratic": np.concatenate([_E3] * 3, axis=1),
+    "cc7": np.concatenate([_E3, _DIAG.T], axis=1),
+    "bcc7": np.concatenate([_DIAG.T, 2 * _E3], axis=1),
 }
 LATTICE_OF = {"tricubic": "cc", "bcc8": "bcc", "fcc6": "fcc", "trilinear": "cc", "bcc4": "bcc",
-              "triquadratic": "cc"}
+              "triquadratic": "cc", "cc7": "cc", "bcc7": "bcc"}
 
 
 def set_option(option: int, value: int) -> None:
@@ -103,6 +105,16 @@ class Spline:
     @classmethod
     def triquadratic(cls):
         return cls(LATTICES["cc"], DIRECTIONS["triquadratic"])
+
+    @classmethod
+    def cc7(cls):
+        """Seven-direction box spline on Z^3 (axes and diagonals), fourth order."""
+        return cls(LATTICES["cc"], DIRECTIONS["cc7"])
+
+    @classmethod
+    def bcc7(cls):
+        """Quartic box spline on BCC (diagonals and 2 e_i), fourth order."""
+        return cls(LATTICES["bcc"], DIRECTIONS["bcc7"])
 
     @classmethod
     def named(cls, name: str):

@@ -33,11 +33,13 @@
 namespace lsp {
 
 // Spline kinds, in the order of the generated kind table (generated/all.h).
-enum Kind : int { kTricubic = 0, kBcc8 = 1, kFcc6 = 2, kTrilinear = 3, kBcc4 = 4, kTriquadratic = 5 };
-static_assert(gen::kNumKinds == 6, "kind table and Kind enum disagree");
+enum Kind : int {
+    kTricubic = 0, kBcc8 = 1, kFcc6 = 2, kTrilinear = 3, kBcc4 = 4, kTriquadratic = 5, kCc7 = 6, kBcc7 = 7
+};
+static_assert(gen::kNumKinds == 8, "kind table and Kind enum disagree");
 
 // Expands X(k) for every spline kind (compile-time dispatch).
-#define LSP_FOR_EACH_KIND(X) X(0) X(1) X(2) X(3) X(4) X(5)
+#define LSP_FOR_EACH_KIND(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
 
 template <int KIND> using TablesOf = typename gen::SplineOf<KIND>::T;
 template <int KIND> using PolyOf = typename gen::SplineOf<KIND>::P;
@@ -160,10 +162,40 @@ LSP_HD int sym_id(const Loc& L) {
     return (L.axis[0] * 3 + L.axis[1]) * 8 + bits;
 }
 
+// The signed permutation y = sort_desc(|x - k|) (Sec. 4.1.3): a 3-comparator
+// network, descending by |d|, carrying each axis' index origins (even / odd
+// offsets), global axis and sign into the reference frame.
+LSP_HD void signed_perm_to_loc(float m[3], int b0[3], int b1[3], int ax[3], float sg[3], Loc& L) {
+#define LSP_CSWAP(i, j)                                                           \
+    {                                                                             \
+        const bool sw = m[i] < m[j];                                              \
+        const float tm = sw ? m[j] : m[i], um = sw ? m[i] : m[j];                 \
+        const int t0 = sw ? b0[j] : b0[i], u0 = sw ? b0[i] : b0[j];               \
+        const int t1 = sw ? b1[j] : b1[i], u1 = sw ? b1[i] : b1[j];               \
+        const int ta = sw ? ax[j] : ax[i], ua = sw ? ax[i] : ax[j];               \
+        const float ts = sw ? sg[j] : sg[i], us = sw ? sg[i] : sg[j];             \
+        m[i] = tm; m[j] = um; b0[i] = t0; b0[j] = u0; b1[i] = t1; b1[j] = u1;     \
+        ax[i] = ta; ax[j] = ua; sg[i] = ts; sg[j] = us;                           \
+    }
+    LSP_CSWAP(0, 1)
+    LSP_CSWAP(1, 2)
+    LSP_CSWAP(0, 1)
+#undef LSP_CSWAP
+    for (int r = 0; r < 3; ++r) {
+        L.y[r] = m[r];
+        L.bidx[0][r] = b0[r];
+        L.bidx[1][r] = b1[r];
+        L.axis[r] = ax[r];
+        L.sgn[r] = sg[r];
+        L.s[r] = sg[r] < 0.0f ? -1 : 1;
+    }
+}
+
 // Z^3 with a parallelepiped ROE (Sec. 4.1.2): the unit cube [0,1)^3 via
-// floor, or the centred cube [-1/2,1/2)^3 via floor(x + 1/2); one
-// sub-region, no symmetry.
-template <class PT, bool CENTRED>
+// floor, or the centred cube [-1/2,1/2)^3 via floor(x + 1/2).  Without
+// symmetry the cube is the sub-region; with signed permutations (SORTED)
+// y = sort_desc(|x - k|) lands in the wedge 0 <= y2 <= y1 <= y0 <= 1/2.
+template <class PT, bool CENTRED, bool SORTED>
 LSP_HD void locate_cc(const PT xin[3], const VolGeom& g, Loc& L) {
     PT x[3], k[3];
     for (int a = 0; a < 3; ++a) {
@@ -173,12 +205,25 @@ LSP_HD void locate_cc(const PT xin[3], const VolGeom& g, Loc& L) {
     int ki[3];
     float d[3];
     finish_common(x, k, g, L, ki, d);
-    for (int a = 0; a < 3; ++a) {
-        L.bidx[0][a] = L.bidx[1][a] = ki[a] + g.pad;
-        L.y[a] = d[a];
-        L.s[a] = 1;
-        L.axis[a] = a;
-        L.sgn[a] = 1.0f;
+    if (SORTED) {
+        float m[3], sg[3];
+        int b0[3], b1[3], ax[3];
+        for (int a = 0; a < 3; ++a) {
+            const bool neg = d[a] < 0.0f;
+            b0[a] = b1[a] = ki[a] + g.pad;
+            m[a] = neg ? -d[a] : d[a];
+            sg[a] = neg ? -1.0f : 1.0f;
+            ax[a] = a;
+        }
+        signed_perm_to_loc(m, b0, b1, ax, sg, L);
+    } else {
+        for (int a = 0; a < 3; ++a) {
+            L.bidx[0][a] = L.bidx[1][a] = ki[a] + g.pad;
+            L.y[a] = d[a];
+            L.s[a] = 1;
+            L.axis[a] = a;
+            L.sgn[a] = 1.0f;
+        }
     }
     L.cb[0] = L.cb[1] = L.cb[2] = L.cb[3] = 0;
     set_axis_layout(g, L);
@@ -220,30 +265,7 @@ LSP_HD void locate_bcc(const PT xin[3], const VolGeom& g, Loc& L) {
         sg[a] = neg ? -1.0f : 1.0f;
         ax[a] = a;
     }
-    // sorting network, descending by |d|, carrying the index origins, axis, sign
-#define LSP_CSWAP(i, j)                                                           \
-    {                                                                             \
-        const bool sw = m[i] < m[j];                                              \
-        const float tm = sw ? m[j] : m[i], um = sw ? m[i] : m[j];                 \
-        const int t0 = sw ? b0[j] : b0[i], u0 = sw ? b0[i] : b0[j];               \
-        const int t1 = sw ? b1[j] : b1[i], u1 = sw ? b1[i] : b1[j];               \
-        const int ta = sw ? ax[j] : ax[i], ua = sw ? ax[i] : ax[j];               \
-        const float ts = sw ? sg[j] : sg[i], us = sw ? sg[i] : sg[j];             \
-        m[i] = tm; m[j] = um; b0[i] = t0; b0[j] = u0; b1[i] = t1; b1[j] = u1;     \
-        ax[i] = ta; ax[j] = ua; sg[i] = ts; sg[j] = us;                           \
-    }
-    LSP_CSWAP(0, 1)
-    LSP_CSWAP(1, 2)
-    LSP_CSWAP(0, 1)
-#undef LSP_CSWAP
-    for (int r = 0; r < 3; ++r) {
-        L.y[r] = m[r];
-        L.bidx[0][r] = b0[r];
-        L.bidx[1][r] = b1[r];
-        L.axis[r] = ax[r];
-        L.sgn[r] = sg[r];
-        L.s[r] = sg[r] < 0.0f ? -1 : 1;
-    }
+    signed_perm_to_loc(m, b0, b1, ax, sg, L);
     L.cb[0] = q * g.es;         // taps with all-even offsets stay in the coset of k
     L.cb[1] = (1 - q) * g.es;   // taps with all-odd offsets are in the other coset
     L.cb[2] = L.cb[3] = L.cb[0];
@@ -309,8 +331,9 @@ template <int KIND, class PT>
 LSP_HD void locate(const PT x[3], const VolGeom& g, Loc& L) {
     using T = TablesOf<KIND>;
     if (T::kLattice == kLatCC) {
-        if (T::kRoe == kRoeRound) locate_cc<PT, true>(x, g, L);
-        else locate_cc<PT, false>(x, g, L);
+        constexpr bool SORTED = T::kSymmetry == kSymSignedPerm;
+        if (T::kRoe == kRoeRound) locate_cc<PT, true, SORTED>(x, g, L);
+        else locate_cc<PT, false, SORTED>(x, g, L);
     } else if (T::kLattice == kLatBCC) {
         locate_bcc(x, g, L);
     } else {
@@ -331,7 +354,8 @@ LSP_HD int tap_offset(const Loc& L, int o0, int o1, int o2, int par) {
     int br = 0, in = 0;
     for (int r = 0; r < 3; ++r) {
         int i;
-        if (LAT == kLatCC) i = L.bidx[0][r] + o[r];
+        if (LAT == kLatCC)
+            i = L.bidx[0][r] + (TablesOf<KIND>::kSymmetry == kSymNone ? o[r] : mul24s(L.s[r], o[r]));
         else if (LAT == kLatBCC) i = L.bidx[par ? 1 : 0][r] + mul24s(L.s[r], o[r] >> 1);
         else i = L.bidx[o[r] & 1][r] + mul24s(L.s[r], o[r] >> 1);
         br += brick_term(i, L.lb[r], L.nbs[r]);

@@ -129,5 +129,29 @@ TRIQUADRATIC = Spec(
     D=(1, 1, 1), shifts=[(0, 0, 0)], roe="round", symmetry="none",
     regions=[Region("centred_cube", _CENTRED_CUBE, (F(1, 5), F(1, 7), F(1, 11)))])
 
-SPECS = {sp.name: sp for sp in sorted((TRICUBIC, BCC8, FCC6, TRILINEAR, BCC4, TRIQUADRATIC),
+# Fourth-order splines of the paper's third comparison (Sec. 5.1).  The
+# seven-direction box spline on Z^3 (the three axes and the four diagonals):
+# centred-cube ROE; the spline is invariant under all signed permutations and
+# its knot planes (y_i in Z + 1/2, y_i +- y_j in Z) miss the interior of the
+# wedge 0 <= y2 <= y1 <= y0 <= 1/2, which is one reference sub-region.  The
+# quartic box spline on BCC (the four diagonals and the three shortest
+# axis-aligned lattice vectors 2 e_i): knot planes y_i in Z, y_i +- y_j in 2Z,
+# so the wedge of the truncated octahedron is again one sub-region.
+CC7 = Spec(
+    name="cc7", kind=6, lattice="cc", s=3, L=[[1, 0, 0], [0, 1, 0], [0, 0, 1]], Xi=E + DIAG,
+    D=(1, 1, 1), shifts=[(0, 0, 0)], roe="round", symmetry="signed_perm",
+    regions=[Region("wedge",
+                    [((1, -1, 0), 0), ((0, 1, -1), 0), ((0, 0, 1), 0), ((-1, 0, 0), _HALF)],
+                    (F(3, 10), F(1, 5), F(1, 10)))])
+
+BCC7 = Spec(
+    name="bcc7", kind=7, lattice="bcc", s=3, L=[[-1, 1, 1], [1, -1, 1], [1, 1, -1]],
+    Xi=DIAG + [(2, 0, 0), (0, 2, 0), (0, 0, 2)],
+    D=(2, 2, 2), shifts=[(0, 0, 0), (1, 1, 1)], roe="voronoi", symmetry="signed_perm",
+    regions=[Region("wedge",
+                    [((1, -1, 0), 0), ((0, 1, -1), 0), ((0, 0, 1), 0),
+                     ((-1, 0, 0), 1), ((-1, -1, -1), F(3, 2))],
+                    (F(1, 2), F(3, 10), F(1, 10)))])
+
+SPECS = {sp.name: sp for sp in sorted((TRICUBIC, BCC8, FCC6, TRILINEAR, BCC4, TRIQUADRATIC, CC7, BCC7),
                                       key=lambda sp: sp.kind)}

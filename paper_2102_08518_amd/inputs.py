@@ -40,6 +40,8 @@ LATTICE = {
     "trilinear": dict(D=1, shifts=[(0, 0, 0)], r=1),
     "bcc4": dict(D=2, shifts=[(0, 0, 0), (1, 1, 1)], r=2),
     "triquadratic": dict(D=1, shifts=[(0, 0, 0)], r=1.5),
+    "cc7": dict(D=1, shifts=[(0, 0, 0)], r=2.5),
+    "bcc7": dict(D=2, shifts=[(0, 0, 0), (1, 1, 1)], r=3),
 }
 
 

@@ -23,7 +23,7 @@ import pytest
 from paper_2102_08518_amd.gen import interp
 from paper_2102_08518_amd.gen.emit import OUT_DIR
 
-NAMES = ["tricubic", "bcc8", "fcc6", "trilinear", "bcc4", "triquadratic"]
+NAMES = ["tricubic", "bcc8", "fcc6", "trilinear", "bcc4", "triquadratic", "cc7", "bcc7"]
 
 HARNESS = r"""
 #include <cmath>

@@ -18,7 +18,7 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 rng = np.random.default_rng(77)
 ORACLE_SPLINE = {"tricubic": oracle.TRICUBIC, "bcc8": oracle.BCC8, "fcc6": oracle.FCC6,
                  "trilinear": oracle.TRILINEAR, "bcc4": oracle.BCC4,
-                 "triquadratic": oracle.TRIQUADRATIC}
+                 "triquadratic": oracle.TRIQUADRATIC, "cc7": oracle.CC7, "bcc7": oracle.BCC7}
 ALL = list(ORACLE_SPLINE)
 
 
@@ -43,7 +43,7 @@ def test_generator_reproduces_fig1_zp_polynomial_exactly():
 
 @pytest.mark.parametrize("name,taps,regions", [("tricubic", 64, 1), ("bcc8", 32, 1), ("fcc6", 16, 2),
                                                ("trilinear", 8, 1), ("bcc4", 4, 1),
-                                               ("triquadratic", 27, 1)])
+                                               ("triquadratic", 27, 1), ("cc7", 53, 1), ("bcc7", 30, 1)])
 def test_stencil_sizes(name, taps, regions):
     """Tricubic: 64 fetches (Sec. 5.1); the FCC cubic spline has two reference
     sub-regions (Sec. 5.1); every stencil has vol(supp)/|det L| sites."""

@@ -18,7 +18,8 @@ from paper_2102_08518_amd import api, inputs
 pytestmark = pytest.mark.gpu
 
 ORC = {"tricubic": oracle.TRICUBIC, "bcc8": oracle.BCC8, "fcc6": oracle.FCC6,
-       "trilinear": oracle.TRILINEAR, "bcc4": oracle.BCC4, "triquadratic": oracle.TRIQUADRATIC}
+       "trilinear": oracle.TRILINEAR, "bcc4": oracle.BCC4, "triquadratic": oracle.TRIQUADRATIC,
+       "cc7": oracle.CC7, "bcc7": oracle.BCC7}
 ALL = list(ORC)
 
 

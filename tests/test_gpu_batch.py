@@ -12,15 +12,21 @@ from paper_2102_08518_amd import api, inputs
 
 pytestmark = pytest.mark.gpu
 
-ORC = {"tricubic": oracle.TRICUBIC, "bcc8": oracle.BCC8, "fcc6": oracle.FCC6}
+ORC = {"tricubic": oracle.TRICUBIC, "bcc8": oracle.BCC8, "fcc6": oracle.FCC6,
+       "trilinear": oracle.TRILINEAR, "bcc4": oracle.BCC4, "triquadratic": oracle.TRIQUADRATIC,
+       "cc7": oracle.CC7, "bcc7": oracle.BCC7}
+MIXED = [("tricubic", "f32", 9, 1000, False), ("bcc8", "f32", 12, 40000, True),
+         ("fcc6", "bf16", 8, 7000, False), ("bcc8", "f16", 7, 0, False),
+         ("tricubic", "f32", 20, 70001, True), ("bcc8", "f32", 10, 513, False),
+         ("fcc6", "f32", 9, 25000, True), ("tricubic", "bf16", 6, 3000, False)]
+OTHER_KINDS = [("cc7", "f32", 10, 20000, True), ("bcc7", "bf16", 9, 9000, False),
+               ("trilinear", "f32", 11, 5000, True), ("bcc4", "f16", 8, 4097, False),
+               ("triquadratic", "f32", 9, 12000, False), ("bcc7", "f32", 7, 333, True),
+               ("cc7", "bf16", 6, 64, False)]
 
 
-def _mixed(device, seed=41):
+def _mixed(device, seed=41, specs=MIXED):
     rng = np.random.default_rng(seed)
-    specs = [("tricubic", "f32", 9, 1000, False), ("bcc8", "f32", 12, 40000, True),
-             ("fcc6", "bf16", 8, 7000, False), ("bcc8", "f16", 7, 0, False),
-             ("tricubic", "f32", 20, 70001, True), ("bcc8", "f32", 10, 513, False),
-             ("fcc6", "f32", 9, 25000, True), ("tricubic", "bf16", 6, 3000, False)]
     vols, pts, grads, cs = [], [], [], []
     for name, st, E, n, g in specs:
         nc = ORC[name].n_cosets
@@ -49,9 +55,10 @@ def _check_against_single(vols, pts, grads, val, grad):
         api.use_mfma(False)
 
 
-def test_batch_matches_single_volume_and_oracle(device):
-    print("case batch mixed", flush=True)
-    vols, pts, grads, cs = _mixed(device)
+@pytest.mark.parametrize("which", ["mixed", "other_kinds"])
+def test_batch_matches_single_volume_and_oracle(device, which):
+    print("case batch", which, flush=True)
+    vols, pts, grads, cs = _mixed(device, specs=MIXED if which == "mixed" else OTHER_KINDS)
     plan = api.BatchPlan(vols, pts, grads, autotune=True)
     assert plan.tile in (1024, 4096, 16384) and plan.blocks >= 1
     val, grad = plan.run()

@@ -18,7 +18,8 @@ from paper_2102_08518_amd import api, inputs
 pytestmark = pytest.mark.gpu
 
 ORC = {"tricubic": oracle.TRICUBIC, "bcc8": oracle.BCC8, "fcc6": oracle.FCC6,
-       "trilinear": oracle.TRILINEAR, "bcc4": oracle.BCC4, "triquadratic": oracle.TRIQUADRATIC}
+       "trilinear": oracle.TRILINEAR, "bcc4": oracle.BCC4, "triquadratic": oracle.TRIQUADRATIC,
+       "cc7": oracle.CC7, "bcc7": oracle.BCC7}
 ALL = list(ORC)
 TORCH_DT = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}
 U_Q = {"f32": 2.0 ** -24, "bf16": 2.0 ** -9, "f16": 2.0 ** -11}

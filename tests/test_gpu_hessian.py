@@ -22,7 +22,7 @@ from paper_2102_08518_amd import api, inputs
 pytestmark = pytest.mark.gpu
 
 ORC = {"tricubic": oracle.TRICUBIC, "bcc8": oracle.BCC8, "fcc6": oracle.FCC6,
-       "triquadratic": oracle.TRIQUADRATIC}
+       "triquadratic": oracle.TRIQUADRATIC, "cc7": oracle.CC7, "bcc7": oracle.BCC7}
 SMOOTH = list(ORC)
 C0 = ["trilinear", "bcc4"]
 TORCH_DT = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}
@@ -112,7 +112,7 @@ def test_hessian_outputs_agree_with_eval_grad(device, name):
     _check_hessian(name, E, cs, x, H1.cpu().numpy().astype(np.float64), TOL * np.abs(cs).max())
 
 
-@pytest.mark.parametrize("name", ["tricubic", "bcc8"])
+@pytest.mark.parametrize("name", ["tricubic", "bcc8", "cc7", "bcc7"])
 def test_hessian_matches_gradient_differences(device, name):
     """For the C^2 splines the Hessian is the derivative of the GPU gradient:
     central differences with FP64 points, step 1e-3."""

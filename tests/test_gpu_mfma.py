@@ -1,5 +1,5 @@
-"""The matrix-core evaluation of the 8-direction BCC spline (monomial
-coefficients A = Wq c / Q on the MFMA units) against the FP64 checker and
+"""The matrix-core evaluation of the one-sub-region BCC splines (8-direction
+and quartic; monomial coefficients A = Wq c / Q on the MFMA units) against the FP64 checker and
 against the per-lane FMA path, for every coefficient storage, value and
 gradient, direct and binned order, and wavefront-ragged point counts
 (lanes without a point still take part in the matrix products).
@@ -28,19 +28,23 @@ def restore_mfma():
     api.use_mfma(False)
 
 
+ORC = {"bcc8": oracle.BCC8, "bcc7": oracle.BCC7}
+
+
+@pytest.mark.parametrize("name", list(ORC))
 @pytest.mark.parametrize("storage", ["f32", "bf16", "f16"])
 @pytest.mark.parametrize("n", [1, 63, 64, 65, 3001])
-def test_mfma_matches_oracle_and_fma_path(device, restore_mfma, storage, n):
-    print("case mfma", storage, n, flush=True)
+def test_mfma_matches_oracle_and_fma_path(device, restore_mfma, name, storage, n):
+    print("case mfma", name, storage, n, flush=True)
     rng = np.random.default_rng(300 + n)
     E = 12
     c = rng.uniform(-1, 1, (2, E, E, E))
-    vol = api.Volume(api.Spline.bcc8(), (E, E, E), storage)
+    vol = api.Volume(api.Spline.named(name), (E, E, E), storage)
     vol.set(torch.tensor(c, dtype=torch.float32, device=device))
     x = rng.uniform(-3, 2 * (E - 1) + 3, (n, 3)).astype(np.float32)
     xt = torch.tensor(x, device=device)
     cs = _stored(c, storage)
-    fref, gref = oracle.evaluate(oracle.BCC8, (E, E, E), list(cs), x.astype(np.float64), grad=True)
+    fref, gref = oracle.evaluate(ORC[name], (E, E, E), list(cs), x.astype(np.float64), grad=True)
     out = {}
     for on in (True, False):
         api.use_mfma(on)
@@ -56,15 +60,16 @@ def test_mfma_matches_oracle_and_fma_path(device, restore_mfma, storage, n):
     assert np.abs(out[True] - out[False]).max() <= 4e-6 * np.abs(cs).max()
 
 
-def test_mfma_special_points(device, restore_mfma):
+@pytest.mark.parametrize("name", list(ORC))
+def test_mfma_special_points(device, restore_mfma, name):
     """NaN -> NaN, far and infinite points -> 0, mixed into full wavefronts
     with ordinary points, on the matrix-core path."""
-    print("case mfma special", flush=True)
+    print("case mfma special", name, flush=True)
     api.use_mfma(True)
     rng = np.random.default_rng(8)
     E = 8
     c = rng.uniform(-1, 1, (2, E, E, E))
-    vol = api.Volume(api.Spline.bcc8(), (E, E, E), "f32")
+    vol = api.Volume(api.Spline.named(name), (E, E, E), "f32")
     vol.set(torch.tensor(c, dtype=torch.float32, device=device))
     x = rng.uniform(0, 2 * (E - 1), (128, 3)).astype(np.float32)
     x[3] = np.nan
@@ -75,7 +80,7 @@ def test_mfma_special_points(device, restore_mfma):
     assert np.isnan(f[3]) and f[40] == 0 and f[70] == 0 and f[100] == 0
     ok = np.ones(128, bool)
     ok[[3, 40, 70, 100]] = False
-    ref = oracle.evaluate(oracle.BCC8, (E, E, E), list(_stored(c, "f32")), x[ok].astype(np.float64))
+    ref = oracle.evaluate(ORC[name], (E, E, E), list(_stored(c, "f32")), x[ok].astype(np.float64))
     assert np.abs(f[ok] - ref).max() <= 2e-6 * np.abs(c).max()
 
 
