@@ -45,35 +45,64 @@ template <> struct Coef<f16_t> {
     }
 };
 
+// Whether the tap loads are also fenced off from the arithmetic after them.
+// With the fence the polynomial starts only once every load is issued; without
+// it the scheduler may start consuming the first taps among the last loads.
+// Chosen per spline and mode from measurements on MI355X (the analogue of the
+// paper's per-architecture parameter exploration, Sec. 5): the fence pays
+// for the 7-direction splines and the BCC8 gradient; the separable splines and
+// the BCC8 value do better without it.
+template <int KIND, int MODE>
+constexpr bool fence_after_loads() {
+    return !TablesOf<KIND>::kTensor && !(KIND == kBcc8 && MODE == kValue);
+}
+
 // Fetch every tap of the union stencil (Algorithm 1's memory lookups through
-// the permuted stencil pi').
-template <int KIND, class CT>
+// the permuted stencil pi').  The gathers are latency-bound, so every address
+// is formed first and the loads are then issued back to back.  Left to itself
+// the scheduler interleaves them with address arithmetic or, to save
+// registers, waits on the first loads before issuing the last (a second
+// memory round trip per point).
+template <int KIND, class CT, bool FENCE_AFTER>
 __device__ __forceinline__ void gather(const Loc& L, __amdgpu_buffer_rsrc_t r, float* c) {
     using T = TablesOf<KIND>;
+    int off[T::kTaps];
 #pragma unroll
     for (int j = 0; j < T::kTaps; ++j)
-        c[j] = Coef<CT>::ld(r, tap_offset<KIND>(L, T::kOff[j][0], T::kOff[j][1], T::kOff[j][2],
-                                                T::kParity[j]));
+        off[j] = tap_offset<KIND>(L, T::kOff[j][0], T::kOff[j][1], T::kOff[j][2], T::kParity[j]);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < T::kTaps; ++j) c[j] = Coef<CT>::ld(r, off[j]);
+    if constexpr (FENCE_AFTER) __builtin_amdgcn_sched_barrier(0);
 }
 
 // Reference polynomial value and gradient (the unrolled reference
 // sub-region loop of Sec. 4.3, generated per spline; two reference
-// sub-regions either branch or evaluate both and select).
+// sub-regions either branch or evaluate both and select).  For the
+// tensor-product splines w holds the 1D weights formed from y before the
+// gather (PolyOf<KIND>::pre), so that work overlaps the loads in flight.
 template <int KIND, bool PREDICATED>
-__device__ __forceinline__ float poly_value(const float* c, const Loc& L) {
-    return PolyOf<KIND>::template value<PREDICATED>(c, L.y[0], L.y[1], L.y[2], L.region);
+__device__ __forceinline__ float poly_value(const float* c, const Loc& L, const float* w) {
+    if constexpr (PolyOf<KIND>::kPre > 0) return PolyOf<KIND>::value_pre(c, w);
+    else return PolyOf<KIND>::template value<PREDICATED>(c, L.y[0], L.y[1], L.y[2], L.region);
 }
 
 template <int KIND, bool PREDICATED>
-__device__ __forceinline__ float poly_value_grad(const float* c, const Loc& L, float* g) {
-    return PolyOf<KIND>::template value_grad<PREDICATED>(c, L.y[0], L.y[1], L.y[2], L.region, g[0],
-                                                          g[1], g[2]);
+__device__ __forceinline__ float poly_value_grad(const float* c, const Loc& L, const float* w, float* g) {
+    if constexpr (PolyOf<KIND>::kPre > 0) return PolyOf<KIND>::value_grad_pre(c, w, g[0], g[1], g[2]);
+    else
+        return PolyOf<KIND>::template value_grad<PREDICATED>(c, L.y[0], L.y[1], L.y[2], L.region, g[0],
+                                                              g[1], g[2]);
 }
 
 template <int KIND, bool PREDICATED>
-__device__ __forceinline__ float poly_value_grad_hess(const float* c, const Loc& L, float* g, float* h) {
-    return PolyOf<KIND>::template value_grad_hess<PREDICATED>(c, L.y[0], L.y[1], L.y[2], L.region,
-                                                               g[0], g[1], g[2], h);
+__device__ __forceinline__ float poly_value_grad_hess(const float* c, const Loc& L, const float* w, float* g,
+                                                      float* h) {
+    if constexpr (PolyOf<KIND>::kPre > 0)
+        return PolyOf<KIND>::value_grad_hess_pre(c, w, g[0], g[1], g[2], h);
+    else
+        return PolyOf<KIND>::template value_grad_hess<PREDICATED>(c, L.y[0], L.y[1], L.y[2], L.region,
+                                                                   g[0], g[1], g[2], h);
 }
 
 // Hessian back to global axes: with y = G (x - k), G a signed permutation,
@@ -138,18 +167,22 @@ __device__ __forceinline__ void eval_at(const PT x[3], int o, const void* __rest
                                         const float* __restrict__ gin,
                                         float* __restrict__ hess = nullptr) {
     using T = TablesOf<KIND>;
+    using P = PolyOf<KIND>;
     Loc L;
     locate<KIND>(x, g, L);
     const __amdgpu_buffer_rsrc_t r = make_rsrc(coef, nbytes);
+    float w[P::kPre > 0 ? P::kPre : 1];
+    if constexpr (P::kPre > 0)
+        P::template pre<MODE == kValue ? 0 : (MODE == kValueGradHess ? 2 : 1)>(L.y[0], L.y[1], L.y[2], w);
     float c[T::kTaps];
-    gather<KIND, CT>(L, r, c);
+    gather<KIND, CT, fence_after_loads<KIND, MODE>()>(L, r, c);
     const float qnan = __builtin_nanf("");
     if (MODE == kValue) {
-        const float f = poly_value<KIND, PREDICATED>(c, L);
+        const float f = poly_value<KIND, PREDICATED>(c, L, w);
         out[o] = L.active ? f : (L.nan ? qnan : 0.0f);
     } else if (MODE == kValueGradHess) {
         float gr[3], gx[3], hr[6], hx[6];
-        const float f = poly_value_grad_hess<KIND, PREDICATED>(c, L, gr, hr);
+        const float f = poly_value_grad_hess<KIND, PREDICATED>(c, L, w, gr, hr);
         grad_to_global(L, gr, gx);
         hess_to_global(L, hr, hx);
         const float fill = L.nan ? qnan : 0.0f;
@@ -161,7 +194,7 @@ __device__ __forceinline__ void eval_at(const PT x[3], int o, const void* __rest
         for (int a = 0; a < 6; ++a) hess[6 * (size_t)o + a] = L.active ? hx[a] : fill;
     } else {
         float gr[3], gx[3];
-        const float f = poly_value_grad<KIND, PREDICATED>(c, L, gr);
+        const float f = poly_value_grad<KIND, PREDICATED>(c, L, w, gr);
         grad_to_global(L, gr, gx);
         const float fill = L.nan ? qnan : 0.0f;
         float scale = 1.0f;

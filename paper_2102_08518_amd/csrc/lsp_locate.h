@@ -104,12 +104,30 @@ struct Loc {
     bool nan;          // a coordinate was NaN
 };
 
+// The layout is wave-uniform: on the device the per-axis values are taken
+// into scalar registers first, so that the per-lane choice below is a
+// register select and never becomes a per-lane load from the kernel
+// arguments (a dependent memory round trip ahead of every gather).
+LSP_HD int uniform_int(int v) {
+#ifdef __HIP_DEVICE_COMPILE__
+    return __builtin_amdgcn_readfirstlane(v);
+#else
+    return v;
+#endif
+}
+
 LSP_HD void set_axis_layout(const VolGeom& g, Loc& L) {
+    int lb[3], nbs[3], lis[3];
+    for (int a = 0; a < 3; ++a) {
+        lb[a] = uniform_int(g.lb[a]);
+        nbs[a] = uniform_int(g.nbs[a]);
+        lis[a] = uniform_int(g.lis[a]);
+    }
     for (int r = 0; r < 3; ++r) {
         const int a = L.axis[r];
-        L.lb[r] = a == 0 ? g.lb[0] : (a == 1 ? g.lb[1] : g.lb[2]);
-        L.nbs[r] = a == 0 ? g.nbs[0] : (a == 1 ? g.nbs[1] : g.nbs[2]);
-        L.lis[r] = a == 0 ? g.lis[0] : (a == 1 ? g.lis[1] : g.lis[2]);
+        L.lb[r] = a == 0 ? lb[0] : (a == 1 ? lb[1] : lb[2]);
+        L.nbs[r] = a == 0 ? nbs[0] : (a == 1 ? nbs[1] : nbs[2]);
+        L.lis[r] = a == 0 ? lis[0] : (a == 1 ? lis[1] : lis[2]);
     }
     L.lbb = g.lbb;
 }

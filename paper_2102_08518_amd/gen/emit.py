@@ -650,59 +650,69 @@ class SplineCode:
             L.append("}")
             L.append("")
         n0, n1, n2 = (len(t) for t in taps1)
+        N = max(n0, n1, n2)
         idx = {o: j for j, o in enumerate(self.union)}
 
         def cidx(a, b, cc):
             return idx[(taps1[0][a], taps1[1][b], taps1[2][cc])]
 
+        def W(o, axis, a):
+            # the 1D weight of derivative order o along axis at its a-th offset
+            return "w[%d]" % ((o * 3 + axis) * N + a)
+
+        # the y-dependent part, separable from the coefficients: the 1D
+        # weights of derivative orders 0..DER, w[(order * 3 + axis) * N + a]
+        L.append("// 1D weights of derivative orders 0..DER along the three axes,")
+        L.append("// w[(order * 3 + axis) * %d + a]: all that depends on y alone" % N)
+        L.append("template <int DER>")
+        L.append("__device__ __forceinline__ void %s_pre(float y0, float y1, float y2, float* __restrict__ w) {" % nm)
+        for i, y in enumerate(("y0", "y1", "y2")):
+            L.append("  %s_w1d_%d(%s, w + %d, DER >= 1 ? w + %d : nullptr, DER >= 2 ? w + %d : nullptr);"
+                     % (nm, i, y, i * N, (3 + i) * N, (6 + i) * N))
+        L.append("}")
+        L.append("")
         # value
-        L.append("__device__ __forceinline__ float %s_eval_r0(const float* __restrict__ c, float y0, float y1, float y2) {" % nm)
-        L.append("  float wx[%d], wy[%d], wz[%d];" % (n0, n1, n2))
-        L.append("  %s_w1d_0(y0, wx, nullptr); %s_w1d_1(y1, wy, nullptr); %s_w1d_2(y2, wz, nullptr);" % (nm, nm, nm))
+        L.append("__device__ __forceinline__ float %s_eval_r0_pre(const float* __restrict__ c, const float* __restrict__ w) {" % nm)
         L.append("  float f = 0.0f;")
         for cc in range(n2):
             L.append("  {")
             L.append("    float r = 0.0f;")
             for b in range(n1):
-                terms = " ".join("")
-                e = "c[%d] * wx[0]" % cidx(0, b, cc)
+                e = "c[%d] * %s" % (cidx(0, b, cc), W(0, 0, 0))
                 for a in range(1, n0):
-                    e = "fmaf(c[%d], wx[%d], %s)" % (cidx(a, b, cc), a, e)
-                L.append("    r = fmaf(%s, wy[%d], r);" % (e, b))
-            L.append("    f = fmaf(r, wz[%d], f);" % cc)
+                    e = "fmaf(c[%d], %s, %s)" % (cidx(a, b, cc), W(0, 0, a), e)
+                L.append("    r = fmaf(%s, %s, r);" % (e, W(0, 1, b)))
+            L.append("    f = fmaf(r, %s, f);" % W(0, 2, cc))
             L.append("  }")
         L.append("  return f;")
         L.append("}")
         L.append("")
         # value + gradient
-        L.append("__device__ __forceinline__ float %s_eval_grad_r0(const float* __restrict__ c, float y0, float y1, float y2," % nm)
-        L.append("                                                float& g0, float& g1, float& g2) {")
-        L.append("  float wx[%d], wy[%d], wz[%d], dx[%d], dy[%d], dz[%d];" % (n0, n1, n2, n0, n1, n2))
-        L.append("  %s_w1d_0(y0, wx, dx); %s_w1d_1(y1, wy, dy); %s_w1d_2(y2, wz, dz);" % (nm, nm, nm))
+        L.append("__device__ __forceinline__ float %s_eval_grad_r0_pre(const float* __restrict__ c, const float* __restrict__ w," % nm)
+        L.append("                                                    float& g0, float& g1, float& g2) {")
         L.append("  float f = 0.0f; g0 = 0.0f; g1 = 0.0f; g2 = 0.0f;")
         for cc in range(n2):
             L.append("  {")
             L.append("    float r = 0.0f, rx = 0.0f, ry = 0.0f;")
             for b in range(n1):
-                e = "c[%d] * wx[0]" % cidx(0, b, cc)
-                ed = "c[%d] * dx[0]" % cidx(0, b, cc)
+                e = "c[%d] * %s" % (cidx(0, b, cc), W(0, 0, 0))
+                ed = "c[%d] * %s" % (cidx(0, b, cc), W(1, 0, 0))
                 for a in range(1, n0):
-                    e = "fmaf(c[%d], wx[%d], %s)" % (cidx(a, b, cc), a, e)
-                    ed = "fmaf(c[%d], dx[%d], %s)" % (cidx(a, b, cc), a, ed)
+                    e = "fmaf(c[%d], %s, %s)" % (cidx(a, b, cc), W(0, 0, a), e)
+                    ed = "fmaf(c[%d], %s, %s)" % (cidx(a, b, cc), W(1, 0, a), ed)
                 L.append("    { const float s = %s, sd = %s;" % (e, ed))
-                L.append("      r = fmaf(s, wy[%d], r); ry = fmaf(s, dy[%d], ry); rx = fmaf(sd, wy[%d], rx); }" % (b, b, b))
-            L.append("    f = fmaf(r, wz[%d], f); g2 = fmaf(r, dz[%d], g2);" % (cc, cc))
-            L.append("    g1 = fmaf(ry, wz[%d], g1); g0 = fmaf(rx, wz[%d], g0);" % (cc, cc))
+                L.append("      r = fmaf(s, %s, r); ry = fmaf(s, %s, ry); rx = fmaf(sd, %s, rx); }"
+                         % (W(0, 1, b), W(1, 1, b), W(0, 1, b)))
+            L.append("    f = fmaf(r, %s, f); g2 = fmaf(r, %s, g2);" % (W(0, 2, cc), W(1, 2, cc)))
+            L.append("    g1 = fmaf(ry, %s, g1); g0 = fmaf(rx, %s, g0);" % (W(0, 2, cc), W(0, 2, cc)))
             L.append("  }")
         L.append("  return f;")
         L.append("}")
         L.append("")
         # value, gradient and Hessian: contractions with the 1D weights of
         # derivative orders (ox, oy, oz), ox + oy + oz <= 2
-        L.append("__device__ __forceinline__ float %s_eval_hess_r0(const float* __restrict__ c, float y0, float y1, float y2," % nm)
-        L.append("                                                float& g0, float& g1, float& g2, float* __restrict__ h) {")
-        L.append("  float wx[3][%d], wy[3][%d], wz[3][%d];" % (n0, n1, n2))
-        L.append("  %s_w1d_0(y0, wx[0], wx[1], wx[2]); %s_w1d_1(y1, wy[0], wy[1], wy[2]); %s_w1d_2(y2, wz[0], wz[1], wz[2]);" % (nm, nm, nm))
+        L.append("__device__ __forceinline__ float %s_eval_hess_r0_pre(const float* __restrict__ c, const float* __restrict__ w," % nm)
+        L.append("                                                    float& g0, float& g1, float& g2, float* __restrict__ h) {")
         orders = [(ox, oy, oz) for ox in range(3) for oy in range(3) for oz in range(3) if ox + oy + oz <= 2]
         pairs = sorted(set((ox, oy) for ox, oy, _ in orders))
         L.append("  float F[%d] = {};" % len(orders))
@@ -712,22 +722,43 @@ class SplineCode:
             for b in range(n1):
                 sums = []
                 for ox in range(3):
-                    e = "c[%d] * wx[%d][0]" % (cidx(0, b, cc), ox)
+                    e = "c[%d] * %s" % (cidx(0, b, cc), W(ox, 0, 0))
                     for a in range(1, n0):
-                        e = "fmaf(c[%d], wx[%d][%d], %s)" % (cidx(a, b, cc), ox, a, e)
+                        e = "fmaf(c[%d], %s, %s)" % (cidx(a, b, cc), W(ox, 0, a), e)
                     sums.append(e)
                 L.append("    { const float s0 = %s, s1 = %s, s2 = %s;" % tuple(sums))
                 for pi, (ox, oy) in enumerate(pairs):
-                    L.append("      r[%d] = fmaf(s%d, wy[%d][%d], r[%d]);" % (pi, ox, oy, b, pi))
+                    L.append("      r[%d] = fmaf(s%d, %s, r[%d]);" % (pi, ox, W(oy, 1, b), pi))
                 L.append("    }")
             for oi, (ox, oy, oz) in enumerate(orders):
-                L.append("    F[%d] = fmaf(r[%d], wz[%d][%d], F[%d]);" % (oi, pairs.index((ox, oy)), oz, cc, oi))
+                L.append("    F[%d] = fmaf(r[%d], %s, F[%d]);" % (oi, pairs.index((ox, oy)), W(oz, 2, cc), oi))
             L.append("  }")
         oid = {o: i for i, o in enumerate(orders)}
         L.append("  g0 = F[%d]; g1 = F[%d]; g2 = F[%d];" % (oid[(1, 0, 0)], oid[(0, 1, 0)], oid[(0, 0, 1)]))
         L.append("  h[0] = F[%d]; h[1] = F[%d]; h[2] = F[%d]; h[3] = F[%d]; h[4] = F[%d]; h[5] = F[%d];" % (
             oid[(2, 0, 0)], oid[(1, 1, 0)], oid[(1, 0, 1)], oid[(0, 2, 0)], oid[(0, 1, 1)], oid[(0, 0, 2)]))
         L.append("  return F[%d];" % oid[(0, 0, 0)])
+        L.append("}")
+        L.append("")
+        # the same from y
+        L.append("__device__ __forceinline__ float %s_eval_r0(const float* __restrict__ c, float y0, float y1, float y2) {" % nm)
+        L.append("  float w[%d];" % (3 * N))
+        L.append("  %s_pre<0>(y0, y1, y2, w);" % nm)
+        L.append("  return %s_eval_r0_pre(c, w);" % nm)
+        L.append("}")
+        L.append("")
+        L.append("__device__ __forceinline__ float %s_eval_grad_r0(const float* __restrict__ c, float y0, float y1, float y2," % nm)
+        L.append("                                                float& g0, float& g1, float& g2) {")
+        L.append("  float w[%d];" % (6 * N))
+        L.append("  %s_pre<1>(y0, y1, y2, w);" % nm)
+        L.append("  return %s_eval_grad_r0_pre(c, w, g0, g1, g2);" % nm)
+        L.append("}")
+        L.append("")
+        L.append("__device__ __forceinline__ float %s_eval_hess_r0(const float* __restrict__ c, float y0, float y1, float y2," % nm)
+        L.append("                                                float& g0, float& g1, float& g2, float* __restrict__ h) {")
+        L.append("  float w[%d];" % (9 * N))
+        L.append("  %s_pre<2>(y0, y1, y2, w);" % nm)
+        L.append("  return %s_eval_hess_r0_pre(c, w, g0, g1, g2, h);" % nm)
         L.append("}")
         L.append("")
         # weights
@@ -803,7 +834,32 @@ def _emit_poly_struct_impl(nm: str, nreg: int) -> List[str]:
     return L
 
 
-SplineCode._emit_poly_struct = lambda self: _emit_poly_struct_impl(self.spec.name, len(self.regions))
+def _emit_poly_struct_full(self) -> List[str]:
+    L = _emit_poly_struct_impl(self.spec.name, len(self.regions))
+    nm = self.spec.name
+    if self.tensor is None:
+        pre = ["  static constexpr int kPre = 0;  // no y-only phase"]
+    else:
+        N = max(len(f) for f in self.tensor)
+        pre = ["  // tensor product: the 1D weights (y alone) can be formed before the",
+               "  // coefficients arrive; kPre floats hold derivative orders 0..2",
+               "  static constexpr int kPre = %d;" % (9 * N),
+               "  template <int DER>",
+               "  static __device__ __forceinline__ void pre(float y0, float y1, float y2, float* __restrict__ w) {",
+               "    %s_pre<DER>(y0, y1, y2, w);" % nm, "  }",
+               "  static __device__ __forceinline__ float value_pre(const float* __restrict__ c, const float* __restrict__ w) {",
+               "    return %s_eval_r0_pre(c, w);" % nm, "  }",
+               "  static __device__ __forceinline__ float value_grad_pre(const float* __restrict__ c, const float* __restrict__ w,",
+               "                                                        float& g0, float& g1, float& g2) {",
+               "    return %s_eval_grad_r0_pre(c, w, g0, g1, g2);" % nm, "  }",
+               "  static __device__ __forceinline__ float value_grad_hess_pre(const float* __restrict__ c, const float* __restrict__ w,",
+               "                                                             float& g0, float& g1, float& g2, float* __restrict__ h) {",
+               "    return %s_eval_hess_r0_pre(c, w, g0, g1, g2, h);" % nm, "  }"]
+    end = L.index("};")
+    return L[:end] + pre + L[end:]
+
+
+SplineCode._emit_poly_struct = _emit_poly_struct_full
 
 
 def emit_kind_map(names) -> str:
