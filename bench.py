@@ -137,6 +137,46 @@ def time_fn(fn, steps, warmup, stream):
     return start.elapsed_time(end) / steps  # ms per call
 
 
+def run_orders(args, dev, stream):
+    """Each spline of the order-2, -3 and -4 comparisons on its equal-memory
+    lattice (about 2.1 M sites): forward (direct and binned order) and
+    value + gradient over 10^6 uniform random points, FP32 coefficients."""
+    import torch
+    from paper_2102_08518_amd import api, inputs
+
+    out_all = {}
+    for order, names in inputs.ORDERS.items():
+        row = {}
+        for name in names:
+            w = inputs.orders_workload(name)
+            E, x = w["E"], w["points"]
+            n = x.shape[0]
+            sp = api.Spline.named(name)
+            vol = api.Volume(sp, (E, E, E), "f32")
+            vol.set(torch.tensor(w["coeffs"], device=dev))
+            xt = torch.tensor(x, device=dev)
+            out = torch.empty(n, dtype=torch.float32, device=dev)
+            ws, _, _ = vol._binned_ws(xt, None)
+            ms_d = time_fn(lambda: vol.eval(xt, out), args.steps, args.warmup, stream)
+            ms_b = time_fn(lambda: vol.eval(xt, out, binned=True, workspace=ws), args.steps,
+                           args.warmup, stream)
+            ms_g = time_fn(lambda: vol.eval_grad(xt), args.steps, args.warmup, stream)
+            fma = sp.info.fma_eval
+            row[name] = {"sites": int(sp.n_cosets * E ** 3), "taps": sp.info.taps,
+                         "fma_per_point": fma,
+                         "fwd_direct_pts_s": round(n / (ms_d * 1e-3)),
+                         "fwd_binned_pts_s": round(n / (ms_b * 1e-3)),
+                         "value_grad_pts_s": round(n / (ms_g * 1e-3)),
+                         "fwd_direct_tflops": round(2 * fma * n / (ms_d * 1e-3) / 1e12, 2)}
+            log("order %d %-12s taps %2d  direct %.3e  binned %.3e  value+grad %.3e points/s"
+                % (order, name, sp.info.taps, n / (ms_d * 1e-3), n / (ms_b * 1e-3), n / (ms_g * 1e-3)))
+            del vol, xt, out, ws
+        out_all[str(order)] = row
+    print(json.dumps({"mode": "orders", "unit": "points/s", "points": 10 ** 6, "storage": "f32",
+                      "steps": args.steps, "warmup": args.warmup, "data": "synthetic",
+                      "lattice_extent": inputs.ORDERS_E, "results": out_all}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,6 +187,10 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device-to-device copy (a kernel of known traffic "
                          "that calibrates hardware byte counters)")
+    ap.add_argument("--orders", action="store_true",
+                    help="instead of the headline line: the order-2/3/4 spline comparisons of the "
+                         "paper's experiments (equal-memory lattices, 10^6 random points), one JSON "
+                         "line with points/s per spline")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/traffic.json from the rocprofv3 output directories of a "
                          "--pmc FETCH_SIZE and a --pmc WRITE_SIZE run of this script (no GPU)")
@@ -164,6 +208,9 @@ def main():
 
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
+    if args.orders:
+        run_orders(args, dev, stream)
+        return
     if args.copy_probe:
         src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)

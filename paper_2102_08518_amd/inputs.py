@@ -117,6 +117,25 @@ def workload2(n: int = 1 << 22, E: int = 64):
     return dict(spline="bcc8", E=E, coeffs=c, points=uniform_points(2, "bcc8", E, n))
 
 
+# Per-coset extents of the equal-memory comparison of Sec. 5: CC 128^3, BCC
+# inside 202^3 (2 cosets of 101^3) and FCC inside 161^3 (4 cosets of 81^3),
+# about 2.1 M sites each.
+ORDERS_E = {"cc": 128, "bcc": 101, "fcc": 81}
+ORDERS = {2: ["trilinear", "bcc4"], 3: ["triquadratic", "fcc6"], 4: ["tricubic", "cc7", "bcc8", "bcc7"]}
+LATTICE_NAME = {"tricubic": "cc", "trilinear": "cc", "triquadratic": "cc", "cc7": "cc",
+                "bcc8": "bcc", "bcc4": "bcc", "bcc7": "bcc", "fcc6": "fcc"}
+
+
+def orders_workload(spline: str, n: int = 10 ** 6):
+    """One spline of the order-2/3/4 comparisons: uniform coefficients in
+    [-1, 1] on the equal-memory lattice, n uniform random points inside it."""
+    E = ORDERS_E[LATTICE_NAME[spline]]
+    nc = len(LATTICE[spline]["shifts"])
+    wl = 10 + sorted(LATTICE_NAME).index(spline)
+    c = rng(wl, 0).uniform(-1, 1, (nc, E, E, E)).astype(np.float32)
+    return dict(spline=spline, E=E, coeffs=c, points=uniform_points(wl, spline, E, n))
+
+
 def ray_points(workload: int, spline: str, E: int, width: int = 512, height: int = 512,
                samples: int = 64, tile: int = 8) -> np.ndarray:
     """Orthographic rays through the interior box along normalize(0.2, 0.1, 1);
