@@ -162,12 +162,20 @@ def run_orders(args, dev, stream):
                            args.warmup, stream)
             ms_g = time_fn(lambda: vol.eval_grad(xt), args.steps, args.warmup, stream)
             fma = sp.info.fma_eval
+            extra = {}
+            if sp.info.n_reference > 1:
+                # the paper's "branchless" variant: both reference polynomials, then a select
+                api.use_predication(True)
+                ms_p = time_fn(lambda: vol.eval(xt, out), args.steps, args.warmup, stream)
+                api.use_predication(False)
+                extra = {"fwd_direct_branch_free_pts_s": round(n / (ms_p * 1e-3))}
+                log("order %d %-12s branch-free direct %.3e points/s" % (order, name, n / (ms_p * 1e-3)))
             row[name] = {"sites": int(sp.n_cosets * E ** 3), "taps": sp.info.taps,
                          "fma_per_point": fma,
                          "fwd_direct_pts_s": round(n / (ms_d * 1e-3)),
                          "fwd_binned_pts_s": round(n / (ms_b * 1e-3)),
                          "value_grad_pts_s": round(n / (ms_g * 1e-3)),
-                         "fwd_direct_tflops": round(2 * fma * n / (ms_d * 1e-3) / 1e12, 2)}
+                         "fwd_direct_tflops": round(2 * fma * n / (ms_d * 1e-3) / 1e12, 2), **extra}
             log("order %d %-12s taps %2d  direct %.3e  binned %.3e  value+grad %.3e points/s"
                 % (order, name, sp.info.taps, n / (ms_d * 1e-3), n / (ms_b * 1e-3), n / (ms_g * 1e-3)))
             del vol, xt, out, ws

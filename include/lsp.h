@@ -106,15 +106,24 @@ const char* lsp_version(void);
  * Process-wide evaluation options (take effect for launches issued after the
  * call; not synchronised with launches in flight on other threads).
  *   LSP_OPT_MFMA: how the monomial coefficients A = W c of one-sub-region
- *     splines with more than 16 taps (bcc8) are formed: 0 (default, or the
- *     value of LSP_MFMA in the environment) per-lane FMAs over the generated
- *     shared-term form of W, 1 matrix cores (MFMA) for every coefficient
- *     storage, 2 matrix cores for BF16/FP16 storage and FMAs for FP32.  Every
- *     setting gives results within the FP32 tolerance of the convolution sum;
- *     other splines, the dL/dx pass and batch plans always use per-lane FMAs.
+ *     splines with more than 16 taps (the BCC 8-direction and quartic
+ *     splines) are formed: 0 (default, or the value of LSP_MFMA in the
+ *     environment) per-lane FMAs over the generated shared-term form of W,
+ *     1 matrix cores (MFMA) for every coefficient storage, 2 matrix cores for
+ *     BF16/FP16 storage and FMAs for FP32.  Every setting gives results
+ *     within the FP32 tolerance of the convolution sum; other splines, the
+ *     dL/dx pass and batch plans always use per-lane FMAs.
+ *   LSP_OPT_PREDICATED: how a spline with two reference sub-region
+ *     polynomials (the FCC 6-direction spline) picks its polynomial in
+ *     lsp_eval, lsp_eval_grad and lsp_eval_hessian: 0 (default, or
+ *     LSP_FCC_PREDICATED=1 in the environment for 1) a branch per point, 1
+ *     evaluate both and select (the branch-free form of Sec. 5.1).  Both give
+ *     the same values up to rounding; the binned, backward and batch paths
+ *     always branch.
  * Returns LSP_E_INVALID_ARG for an unknown option or value.
  */
 #define LSP_OPT_MFMA 1
+#define LSP_OPT_PREDICATED 2
 lsp_status lsp_set_option(int option, int value);
 
 /* --------------------------------------------------------------- splines */

@@ -42,8 +42,15 @@ LATTICE_OF = {"tricubic": "cc", "bcc8": "bcc", "fcc6": "fcc", "trilinear": "cc",
 
 
 def set_option(option: int, value: int) -> None:
-    """lsp_set_option: process-wide evaluation options (N.LSP_OPT_MFMA)."""
+    """lsp_set_option: process-wide evaluation options (N.LSP_OPT_MFMA,
+    N.LSP_OPT_PREDICATED)."""
     N.check(N.lib().lsp_set_option(option, value))
+
+
+def use_predication(on: bool) -> None:
+    """Branch-free (both polynomials, select) or branchy evaluation of the
+    two-polynomial FCC spline in the direct entry points."""
+    set_option(N.LSP_OPT_PREDICATED, 1 if on else 0)
 
 
 def use_mfma(on) -> None:

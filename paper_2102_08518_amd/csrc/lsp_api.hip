@@ -190,7 +190,13 @@ int elem_size(int ctype) { return ctype == lsp::kCF32 ? 4 : 2; }
 // a tuning knob that lowers occupancy (fewer waves share each CU's L1).
 // FCC 6-direction: evaluate both reference polynomials and select
 // (LSP_FCC_PREDICATED=1) instead of branching on the sub-region.
+// Branch-free evaluation of splines with two reference polynomials
+// (LSP_OPT_PREDICATED; -1: not set, the environment's LSP_FCC_PREDICATED).
+std::atomic<int> g_opt_pred{-1};
+
 bool fcc_predicated() {
+    const int o = g_opt_pred.load(std::memory_order_relaxed);
+    if (o >= 0) return o == 1;
     static const bool v = [] {
         const char* env = getenv("LSP_FCC_PREDICATED");
         return env && env[0] == '1';
@@ -344,6 +350,11 @@ lsp_status lsp_set_option(int option, int value) {
     if (option == LSP_OPT_MFMA) {
         if (value < 0 || value > 2) return fail(LSP_E_INVALID_ARG, "LSP_OPT_MFMA takes 0, 1 or 2");
         g_opt_mfma.store(value, std::memory_order_relaxed);
+        return LSP_OK;
+    }
+    if (option == LSP_OPT_PREDICATED) {
+        if (value < 0 || value > 1) return fail(LSP_E_INVALID_ARG, "LSP_OPT_PREDICATED takes 0 or 1");
+        g_opt_pred.store(value, std::memory_order_relaxed);
         return LSP_OK;
     }
     return fail(LSP_E_INVALID_ARG, "unknown option %d", option);

@@ -213,3 +213,34 @@ def test_binned_path_at_full_size(device):
     idx = np.random.default_rng(9).choice(x.shape[0], 1000, replace=False)
     ref = oracle.evaluate(oracle.BCC8, (E, E, E), list(_stored(c, "f32")), x[idx].astype(np.float64))
     assert np.abs(f.cpu().numpy()[idx] - ref).max() <= 2e-6 * np.abs(c).max()
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_fcc6_branch_free_matches_branchy(device, storage):
+    """The two-polynomial FCC spline evaluated branch-free (both reference
+    polynomials, then a select) and with a branch per point: same values,
+    gradients and Hessians up to rounding, both against the checker."""
+    print("case fcc6 predication", storage, flush=True)
+    rng = np.random.default_rng(55)
+    E = 10
+    c = rng.uniform(-1, 1, (4, E, E, E))
+    x = _points("fcc6", E, 4099, rng)
+    vol = _mk("fcc6", E, c, storage, device)
+    xt = torch.tensor(x, device=device)
+    res = {}
+    try:
+        for pred in (False, True):
+            api.use_predication(pred)
+            res[pred] = (vol.eval(xt), *vol.eval_grad(xt), vol.eval_hessian(xt)[2])
+    finally:
+        api.use_predication(False)
+    cs = _stored(c, storage)
+    fref, gref = oracle.evaluate(oracle.FCC6, (E, E, E), list(cs), x.astype(np.float64), grad=True)
+    cm = np.abs(cs).max()
+    for pred in (False, True):
+        f, v, g, _ = res[pred]
+        assert np.abs(f.cpu().numpy() - fref).max() <= 2e-6 * cm
+        assert np.abs(v.cpu().numpy() - fref).max() <= 2e-6 * cm
+        assert np.abs(g.cpu().numpy() - gref).max() <= 2e-5 * cm
+    for a, b in zip(res[False], res[True]):
+        assert torch.allclose(a, b, rtol=0, atol=4e-6 * float(cm)), float((a - b).abs().max())

@@ -79,6 +79,11 @@ def test_unsupported_and_invalid_arguments():
     assert lib.lsp_set_option(N.LSP_OPT_MFMA, 3) == 1
     assert lib.lsp_set_option(999, 0) == 1
     assert lib.lsp_set_option(N.LSP_OPT_MFMA, 2) == 0
+    assert lib.lsp_set_option(N.LSP_OPT_PREDICATED, 2) == 1
+    assert lib.lsp_set_option(N.LSP_OPT_PREDICATED, 1) == 0
+    # back to the defaults for whatever runs next in this process
+    assert lib.lsp_set_option(N.LSP_OPT_MFMA, 0) == 0
+    assert lib.lsp_set_option(N.LSP_OPT_PREDICATED, 0) == 0
 
 
 def _site_offset(tab, geo, n):
