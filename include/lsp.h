@@ -120,10 +120,20 @@ const char* lsp_version(void);
  *     evaluate both and select (the branch-free form of Sec. 5.1).  Both give
  *     the same values up to rounding; the binned, backward and batch paths
  *     always branch.
+ *   LSP_OPT_SPLIT_MAXN: lsp_eval, lsp_eval_grad and the dL/dx of
+ *     lsp_backward for the separable
+ *     splines (trilinear, triquadratic, tricubic) use four lanes per point,
+ *     one per z-slab of the stencil, when N is at most this count (0 never;
+ *     -1, the default unless LSP_SPLIT_MAXN is set in the environment,
+ *     restores each spline's own measured limit: always for tricubic, 2^18
+ *     points for triquadratic, 2^17 for trilinear).  Four times the
+ *     wavefronts hide the gather latency.  Results agree with the one-lane
+ *     kernel up to the order of the last additions.
  * Returns LSP_E_INVALID_ARG for an unknown option or value.
  */
 #define LSP_OPT_MFMA 1
 #define LSP_OPT_PREDICATED 2
+#define LSP_OPT_SPLIT_MAXN 3
 lsp_status lsp_set_option(int option, int value);
 
 /* --------------------------------------------------------------- splines */
@@ -286,7 +296,9 @@ typedef struct lsp_batch_plan lsp_batch_plan;  /* opaque: bound work list + capt
 /*
  * Plan the evaluation of n_vol volumes of uneven size in one persistent
  * launch (the per-point work of lsp_eval / lsp_eval_grad, Algorithm 1, for
- * every volume).  Per volume v (host arrays of n_vol entries):
+ * every volume, one lane per point: the results equal those of lsp_eval and
+ * lsp_eval_grad with LSP_OPT_SPLIT_MAXN = 0, and agree up to rounding of the
+ * last additions otherwise).  Per volume v (host arrays of n_vol entries):
  *   vols[v]  volume handle (any spline and storage type; must outlive the plan
  *            and keep its coefficients bound)
  *   pts[v]   device, N[v]*3 FP32 points

@@ -30,6 +30,7 @@ EXPORTS = ("lsp_status_string", "lsp_last_error", "lsp_version", "lsp_set_option
 LSP_BATCH_AUTOTUNE = 1
 LSP_OPT_MFMA = 1
 LSP_OPT_PREDICATED = 2
+LSP_OPT_SPLIT_MAXN = 3
 
 
 class LspError(RuntimeError):

@@ -53,6 +53,12 @@ def use_predication(on: bool) -> None:
     set_option(N.LSP_OPT_PREDICATED, 1 if on else 0)
 
 
+def set_split_maxn(n: int) -> None:
+    """Largest point count the separable splines evaluate with four lanes
+    per point (0: never; -1: each spline's measured default)."""
+    set_option(N.LSP_OPT_SPLIT_MAXN, int(n))
+
+
 def use_mfma(on) -> None:
     """How the monomial coefficients of the splines with a matrix-core form
     are evaluated: False (per-lane FMAs, the default), True (matrix cores) or

@@ -23,6 +23,7 @@
 #include "lsp_binned.h"
 #include "lsp_kernels.h"
 #include "lsp_mfma.h"
+#include "lsp_split.h"
 
 namespace lsp {
 
@@ -157,6 +158,23 @@ __global__ __launch_bounds__(256) void k_eval_binned(const Rec<PT>* __restrict__
     eval_at<KIND, CT, PT, MODE, false>(q.x, q.i, coef, nbytes, g, out, grad, nullptr);
 }
 
+// Four lanes per record for the separable splines (the same per-point body
+// as the direct entry points, so the results agree bit for bit).
+template <int KIND, class CT, class PT, int MODE>
+__global__ __launch_bounds__(256) void k_eval_binned_split(const Rec<PT>* __restrict__ rec, int N,
+                                                           const void* __restrict__ coef,
+                                                           unsigned nbytes, VolGeom g,
+                                                           float* __restrict__ out,
+                                                           float* __restrict__ grad) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long p = t >> 2;
+    const bool has = p < N;
+    Rec<PT> q{};
+    if (has) q = rec[p];
+    eval_split_at<KIND, CT, PT, MODE>(q.x, q.i, has, (int)(t & 3), coef, nbytes, g, out, grad,
+                                      nullptr);
+}
+
 // Matrix-core evaluation in bin order; block b handles records
 // [b * 256 * ppt, (b + 1) * 256 * ppt), 256 at a time.
 template <int KIND, class CT, class PT, int MODE>
@@ -227,6 +245,18 @@ hipError_t run(const BinnedArgs& a, const Parts& q) {
                 hipLaunchKernelGGL((k_eval_binned_mfma<KIND, CT, PT, kValue>), dim3(mblocks),
                                    dim3(256), 0, a.stream, rec, N, ppt, a.coef, a.nbytes, a.g, a.out,
                                    a.grad);
+            return hipGetLastError();
+        }
+    }
+    if constexpr (split_eligible<KIND>()) {
+        if (N <= split_limit<KIND>(a.split_maxn)) {
+            const int sblocks = (int)(((long long)N * kSplitLanes + 255) / 256);
+            if (a.grad)
+                hipLaunchKernelGGL((k_eval_binned_split<KIND, CT, PT, kValueGrad>), dim3(sblocks),
+                                   dim3(256), 0, a.stream, rec, N, a.coef, a.nbytes, a.g, a.out, a.grad);
+            else
+                hipLaunchKernelGGL((k_eval_binned_split<KIND, CT, PT, kValue>), dim3(sblocks),
+                                   dim3(256), 0, a.stream, rec, N, a.coef, a.nbytes, a.g, a.out, a.grad);
             return hipGetLastError();
         }
     }

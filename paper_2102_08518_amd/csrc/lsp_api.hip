@@ -190,6 +190,23 @@ int elem_size(int ctype) { return ctype == lsp::kCF32 ? 4 : 2; }
 // a tuning knob that lowers occupancy (fewer waves share each CU's L1).
 // FCC 6-direction: evaluate both reference polynomials and select
 // (LSP_FCC_PREDICATED=1) instead of branching on the sub-region.
+// Largest point count evaluated with four lanes per point by the separable
+// splines (LSP_OPT_SPLIT_MAXN, else LSP_SPLIT_MAXN in the environment; -1
+// when neither is set: each spline's measured default).
+std::atomic<int> g_opt_split{-2};
+
+int split_maxn() {
+    const int o = g_opt_split.load(std::memory_order_relaxed);
+    if (o >= -1) return o;
+    static const int v = [] {
+        const char* env = getenv("LSP_SPLIT_MAXN");
+        if (!env) return -1;
+        const long x = strtol(env, nullptr, 10);
+        return (int)(x < 0 ? 0 : (x > 0x7fffffffL ? 0x7fffffffL : x));
+    }();
+    return v;
+}
+
 // Branch-free evaluation of splines with two reference polynomials
 // (LSP_OPT_PREDICATED; -1: not set, the environment's LSP_FCC_PREDICATED).
 std::atomic<int> g_opt_pred{-1};
@@ -350,6 +367,11 @@ lsp_status lsp_set_option(int option, int value) {
     if (option == LSP_OPT_MFMA) {
         if (value < 0 || value > 2) return fail(LSP_E_INVALID_ARG, "LSP_OPT_MFMA takes 0, 1 or 2");
         g_opt_mfma.store(value, std::memory_order_relaxed);
+        return LSP_OK;
+    }
+    if (option == LSP_OPT_SPLIT_MAXN) {
+        if (value < -1) return fail(LSP_E_INVALID_ARG, "LSP_OPT_SPLIT_MAXN takes a count >= 0, or -1");
+        g_opt_split.store(value, std::memory_order_relaxed);
         return LSP_OK;
     }
     if (option == LSP_OPT_PREDICATED) {
@@ -522,6 +544,7 @@ static lsp_status run_eval(const lsp_volume* vol, const void* pts, lsp_dtype pd,
     a.stream = stream;
     a.lds_bytes = eval_lds_bytes();
     a.mfma = mfma_for(vol->ctype);
+    a.split_maxn = split_maxn();
     hipError_t e = hipSuccess;
     bool found = false;
 #define LSP_RUN(k) \
@@ -621,6 +644,7 @@ lsp_status lsp_eval_binned(const lsp_volume* vol, const void* pts, lsp_dtype pts
     a.ws_bytes = ws_bytes;
     a.stream = stream;
     a.mfma = mfma_for(vol->ctype);
+    a.split_maxn = split_maxn();
     hipError_t e = lsp::launch_binned(a);
     if (e != hipSuccess) return hip_fail(e, "binned evaluation launch");
     return LSP_OK;

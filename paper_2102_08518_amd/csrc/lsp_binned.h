@@ -48,6 +48,7 @@ struct BinnedArgs {
     size_t ws_bytes;
     hipStream_t stream;
     bool mfma;     // matrix-core evaluation where the spline has one
+    int split_maxn;  // separable splines: four lanes per record when N <= this (-1: default)
 };
 
 size_t binned_workspace_bytes(const BinGeom& bg, int N, bool pts_f64);

@@ -5,6 +5,7 @@
 #include "lsp_kernels.h"
 #include "lsp_launch.h"
 #include "lsp_mfma.h"
+#include "lsp_split.h"
 
 namespace lsp {
 
@@ -26,6 +27,16 @@ hipError_t launch_one(const EvalArgs& a) {
             hipLaunchKernelGGL((k_eval_mfma<KIND, CT, PT, MODE>), dim3(blocks), dim3(kBlock), 0,
                                a.stream, static_cast<const PT*>(a.pts), a.N, ppt, a.coef, a.nbytes,
                                a.g, a.out, a.grad);
+            return hipGetLastError();
+        }
+    }
+    if constexpr (split_eligible<KIND>() && MODE != kValueGradHess) {
+        if (a.N <= split_limit<KIND>(a.split_maxn)) {
+            const long long lanes = (long long)a.N * kSplitLanes;
+            const int blocks = (int)((lanes + kBlock - 1) / kBlock);
+            hipLaunchKernelGGL((k_eval_split<KIND, CT, PT, MODE>), dim3(blocks), dim3(kBlock), 0, a.stream,
+                               static_cast<const PT*>(a.pts), a.N, a.coef, a.nbytes, a.g, a.out, a.grad,
+                               a.gin);
             return hipGetLastError();
         }
     }

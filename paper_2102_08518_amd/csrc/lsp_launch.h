@@ -29,6 +29,8 @@ struct EvalArgs {
     hipStream_t stream;
     unsigned lds_bytes;  // dynamic LDS per workgroup (occupancy control), usually 0
     bool mfma;           // matrix-core path where the spline has one (kValue, kValueGrad)
+    int split_maxn;      // separable splines: four lanes per point when N <= split_maxn
+                         // (-1: the spline's measured default)
 };
 
 // Defined in lsp_dispatch.h and instantiated once per spline kind in its own

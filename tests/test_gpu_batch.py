@@ -43,7 +43,9 @@ def _mixed(device, seed=41, specs=MIXED):
 
 
 def _check_against_single(vols, pts, grads, val, grad):
+    # the batch runs the one-lane body of every spline
     api.use_mfma(False)
+    api.set_split_maxn(0)
     try:
         for v, p, g, a, b in zip(vols, pts, grads, val, grad):
             if g:
@@ -53,6 +55,7 @@ def _check_against_single(vols, pts, grads, val, grad):
                 assert torch.equal(a, v.eval(p))
     finally:
         api.use_mfma(False)
+        api.set_split_maxn(-1)
 
 
 @pytest.mark.parametrize("which", ["mixed", "other_kinds"])

@@ -244,3 +244,35 @@ def test_fcc6_branch_free_matches_branchy(device, storage):
         assert np.abs(g.cpu().numpy() - gref).max() <= 2e-5 * cm
     for a, b in zip(res[False], res[True]):
         assert torch.allclose(a, b, rtol=0, atol=4e-6 * float(cm)), float((a - b).abs().max())
+
+
+@pytest.mark.parametrize("name", ["tricubic", "triquadratic", "trilinear"])
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_four_lanes_per_point_matches_one_lane(device, name, storage):
+    """Small launches of the separable splines use four lanes per point
+    (one z-slab each, summed across the quad); against the one-lane kernel
+    and the checker, for values and gradients, FP32 and FP64 points, with a
+    ragged count that leaves a partial quad group and a partial block."""
+    print("case split lanes", name, storage, flush=True)
+    rng = np.random.default_rng(77)
+    E = 11
+    c = rng.uniform(-1, 1, (1, E, E, E))
+    x = _points(name, E, 4093, rng)
+    vol = _mk(name, E, c, storage, device)
+    cs = _stored(c, storage)
+    for pdt in (torch.float32, torch.float64):
+        xt = torch.tensor(x, dtype=pdt, device=device)
+        res = {}
+        try:
+            for maxn in (1 << 30, 0):
+                api.set_split_maxn(maxn)
+                res[maxn] = (vol.eval(xt), *vol.eval_grad(xt))
+        finally:
+            api.set_split_maxn(-1)
+        fref, gref = oracle.evaluate(ORC[name], (E, E, E), list(cs), x.astype(np.float64), grad=True)
+        for maxn, (f, v, g) in res.items():
+            assert np.abs(f.cpu().numpy() - fref).max() <= 2e-6, (maxn, pdt)
+            assert torch.equal(f, v)
+            assert np.abs(g.cpu().numpy() - gref).max() <= 2e-5, (maxn, pdt)
+        for a, b in zip(res[1 << 30], res[0]):
+            assert torch.allclose(a, b, rtol=0, atol=2e-6), float((a - b).abs().max())

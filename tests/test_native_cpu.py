@@ -84,6 +84,8 @@ def test_unsupported_and_invalid_arguments():
     # back to the defaults for whatever runs next in this process
     assert lib.lsp_set_option(N.LSP_OPT_MFMA, 0) == 0
     assert lib.lsp_set_option(N.LSP_OPT_PREDICATED, 0) == 0
+    assert lib.lsp_set_option(N.LSP_OPT_SPLIT_MAXN, -2) == 1
+    assert lib.lsp_set_option(N.LSP_OPT_SPLIT_MAXN, -1) == 0
 
 
 def _site_offset(tab, geo, n):
