@@ -296,9 +296,10 @@ typedef struct lsp_batch_plan lsp_batch_plan;  /* opaque: bound work list + capt
 /*
  * Plan the evaluation of n_vol volumes of uneven size in one persistent
  * launch (the per-point work of lsp_eval / lsp_eval_grad, Algorithm 1, for
- * every volume, one lane per point: the results equal those of lsp_eval and
- * lsp_eval_grad with LSP_OPT_SPLIT_MAXN = 0, and agree up to rounding of the
- * last additions otherwise).  Per volume v (host arrays of n_vol entries):
+ * every volume, with the per-point body those entry points use for the
+ * volume's point count under the LSP_OPT_SPLIT_MAXN setting in force when
+ * the plan is created, so the results are the same).  Per volume v (host
+ * arrays of n_vol entries):
  *   vols[v]  volume handle (any spline and storage type; must outlive the plan
  *            and keep its coefficients bound)
  *   pts[v]   device, N[v]*3 FP32 points

@@ -14,6 +14,7 @@
 
 #include "lsp_batch.h"
 #include "lsp_kernels.h"
+#include "lsp_split.h"
 
 namespace lsp {
 
@@ -25,8 +26,30 @@ __global__ void k_batch_reset(int* counters, int n) {
     for (int i = 0; i < n; ++i) counters[i] = 0;
 }
 
+// The points of one item with the per-point body lsp_eval uses for a volume
+// of v.N points: four lanes per point for the separable splines up to their
+// limit (split_maxn, -1 for the spline's default), else one lane.  The loop
+// trip count is uniform over the workgroup, so every lane reaches the quad
+// sums of the split body.
 template <int KIND, class CT, int MODE>
-__device__ __forceinline__ void run_item(const BatchVol& v, int start, int count) {
+__device__ __forceinline__ void run_item(const BatchVol& v, int start, int count, int split_maxn) {
+    if constexpr (split_eligible<KIND>()) {
+        const int lim = split_maxn >= 0 ? split_maxn : split_default_maxn<KIND>();
+        if (v.N <= lim) {
+            const int lanes = count * kSplitLanes;
+#pragma unroll 1
+            for (int q = 0; q < lanes; q += kBatchBlock) {
+                const int t = q + (int)threadIdx.x;
+                const bool has = t < lanes;
+                const int p = start + (t >> 2);
+                float x[3] = {0.0f, 0.0f, 0.0f};
+                if (has) load_point(v.pts, p, x);
+                eval_split_at<KIND, CT, float, MODE>(x, p, has, t & 3, v.coef, v.nbytes, v.g, v.val,
+                                                     v.grad, nullptr);
+            }
+            return;
+        }
+    }
     const int end = start + count;
 #pragma unroll 1
     for (int p = start + (int)threadIdx.x; p < end; p += kBatchBlock)
@@ -37,7 +60,8 @@ __device__ __forceinline__ void run_item(const BatchVol& v, int start, int count
 template <int KIND, class CT, int MODE>
 __global__ __launch_bounds__(kBatchBlock) void k_batch(const BatchVol* __restrict__ vols,
                                                        const BatchItem* __restrict__ items,
-                                                       int n_items, int* __restrict__ counter) {
+                                                       int n_items, int* __restrict__ counter,
+                                                       int split_maxn) {
     __shared__ int s_item;
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
@@ -51,30 +75,30 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch(const BatchVol* __restric
         // by reference: the layout fields selected per axis are then read
         // from the descriptor in memory, not from a private copy
         const BatchVol& v = vols[w.vol];
-        run_item<KIND, CT, MODE>(v, w.start, w.count);
+        run_item<KIND, CT, MODE>(v, w.start, w.count, split_maxn);
     }
 }
 
 template <int KIND, class CT>
 hipError_t launch_group_ct(const BatchVol* vols, const BatchItem* items, const BatchGroup& gr,
-                           int* counter, int blocks, hipStream_t stream) {
+                           int* counter, int blocks, int split_maxn, hipStream_t stream) {
     const int b = blocks < gr.count ? blocks : gr.count;
     if (gr.grad)
         hipLaunchKernelGGL((k_batch<KIND, CT, kValueGrad>), dim3(b), dim3(kBatchBlock), 0, stream,
-                           vols, items + gr.first, gr.count, counter);
+                           vols, items + gr.first, gr.count, counter, split_maxn);
     else
         hipLaunchKernelGGL((k_batch<KIND, CT, kValue>), dim3(b), dim3(kBatchBlock), 0, stream, vols,
-                           items + gr.first, gr.count, counter);
+                           items + gr.first, gr.count, counter, split_maxn);
     return hipGetLastError();
 }
 
 template <int KIND>
 hipError_t launch_group(const BatchVol* vols, const BatchItem* items, const BatchGroup& gr,
-                        int* counter, int blocks, hipStream_t stream) {
+                        int* counter, int blocks, int split_maxn, hipStream_t stream) {
     switch (gr.ctype) {
-        case kCF32: return launch_group_ct<KIND, float>(vols, items, gr, counter, blocks, stream);
-        case kCBF16: return launch_group_ct<KIND, bf16_t>(vols, items, gr, counter, blocks, stream);
-        case kCF16: return launch_group_ct<KIND, f16_t>(vols, items, gr, counter, blocks, stream);
+        case kCF32: return launch_group_ct<KIND, float>(vols, items, gr, counter, blocks, split_maxn, stream);
+        case kCBF16: return launch_group_ct<KIND, bf16_t>(vols, items, gr, counter, blocks, split_maxn, stream);
+        case kCF16: return launch_group_ct<KIND, f16_t>(vols, items, gr, counter, blocks, split_maxn, stream);
     }
     return hipErrorInvalidValue;
 }
@@ -82,7 +106,7 @@ hipError_t launch_group(const BatchVol* vols, const BatchItem* items, const Batc
 }  // namespace
 
 hipError_t launch_batch(const BatchVol* vols, const BatchItem* items, const BatchGroup* groups,
-                        int n_groups, int* counters, int blocks, hipStream_t stream) {
+                        int n_groups, int* counters, int blocks, int split_maxn, hipStream_t stream) {
     if (n_groups <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, stream, counters, n_groups);
     hipError_t e = hipGetLastError();
@@ -91,7 +115,7 @@ hipError_t launch_batch(const BatchVol* vols, const BatchItem* items, const Batc
         if (gr.count <= 0) continue;
         e = hipErrorInvalidValue;
 #define LSP_GROUP(k) \
-        if (gr.kind == k) e = launch_group<k>(vols, items, gr, counters + gi, blocks, stream);
+        if (gr.kind == k) e = launch_group<k>(vols, items, gr, counters + gi, blocks, split_maxn, stream);
         LSP_FOR_EACH_KIND(LSP_GROUP)
 #undef LSP_GROUP
     }

@@ -832,7 +832,8 @@ lsp_status lsp_batch_plan_create(int n_vol, const lsp_volume* const* vols, const
     if (e != hipSuccess) { destroy_plan(p); return hip_fail(e, "hipMemcpy(vols)"); }
 
     // signature of the batch for the tuning cache: kinds, storage, modes, sizes
-    std::string sig = std::to_string(ncu) + ":";
+    const int smax = split_maxn();
+    std::string sig = std::to_string(ncu) + ":" + std::to_string(smax) + ":";
     for (const lsp::BatchVol& b : hv)
         sig += std::to_string(b.kind) + "/" + std::to_string(b.ctype) + "/" + (b.grad ? "g" : "v") +
                "/" + std::to_string(b.N) + "/" + std::to_string(b.nbytes) + ";";
@@ -858,11 +859,11 @@ lsp_status lsp_batch_plan_create(int n_vol, const lsp_volume* const* vols, const
             for (int bi = 0; bi < 3; ++bi) {
                 const int blocks = std::max(1, std::min(ncu * bpcs[bi], p->n_items));
                 e = lsp::launch_batch(p->d_vols, p->d_items, p->groups.data(), (int)p->groups.size(),
-                                      p->d_counter, blocks, stream);
+                                      p->d_counter, blocks, smax, stream);
                 if (e == hipSuccess) e = hipEventRecord(t0, stream);
                 for (int r = 0; r < 3 && e == hipSuccess; ++r)
                     e = lsp::launch_batch(p->d_vols, p->d_items, p->groups.data(),
-                                          (int)p->groups.size(), p->d_counter, blocks, stream);
+                                          (int)p->groups.size(), p->d_counter, blocks, smax, stream);
                 if (e == hipSuccess) e = hipEventRecord(t1, stream);
                 if (e == hipSuccess) e = hipEventSynchronize(t1);
                 float ms = 0;
@@ -891,7 +892,7 @@ lsp_status lsp_batch_plan_create(int n_vol, const lsp_volume* const* vols, const
     if (e == hipSuccess) e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
         hipError_t el = lsp::launch_batch(p->d_vols, p->d_items, p->groups.data(),
-                                          (int)p->groups.size(), p->d_counter, p->blocks, p->cap);
+                                          (int)p->groups.size(), p->d_counter, p->blocks, smax, p->cap);
         e = hipStreamEndCapture(p->cap, &p->graph);
         if (e == hipSuccess) e = el;
     }

@@ -38,8 +38,10 @@ struct BatchGroup {
 // Reset the groups' work counters (device, n_groups ints), then run one
 // persistent kernel per group with at most `blocks` workgroups.  All are
 // plain kernel launches (graph-capturable); groups is host memory.
+// split_maxn: the four-lanes-per-point limit of the separable splines, as
+// for the direct entry points (-1: each spline's default).
 hipError_t launch_batch(const BatchVol* vols, const BatchItem* items, const BatchGroup* groups,
-                        int n_groups, int* counters, int blocks, hipStream_t stream);
+                        int n_groups, int* counters, int blocks, int split_maxn, hipStream_t stream);
 int batch_block_threads();
 
 }  // namespace lsp

@@ -1,6 +1,6 @@
 """GPU parity of the batched persistent launch (one graph replay evaluates
 many volumes of uneven size): every volume's outputs equal the single-volume
-per-lane FMA kernels' (the batch runs that body for every spline) and match
+per-lane FMA kernels' (the batch runs the same per-point body) and match
 the FP64 checker on samples; graph replays see the current contents of the
 bound buffers."""
 import numpy as np
@@ -43,9 +43,10 @@ def _mixed(device, seed=41, specs=MIXED):
 
 
 def _check_against_single(vols, pts, grads, val, grad):
-    # the batch runs the one-lane body of every spline
+    # the batch runs the per-point body the single-volume entry points use
+    # for each volume's size (four lanes per point for the separable splines
+    # up to their limit), without matrix cores
     api.use_mfma(False)
-    api.set_split_maxn(0)
     try:
         for v, p, g, a, b in zip(vols, pts, grads, val, grad):
             if g:
@@ -55,13 +56,22 @@ def _check_against_single(vols, pts, grads, val, grad):
                 assert torch.equal(a, v.eval(p))
     finally:
         api.use_mfma(False)
+
+
+@pytest.mark.parametrize("which", ["mixed", "other_kinds", "one_lane"])
+def test_batch_matches_single_volume_and_oracle(device, which):
+    """one_lane: with four lanes per point switched off the plan follows."""
+    print("case batch", which, flush=True)
+    if which == "one_lane":
+        api.set_split_maxn(0)
+    try:
+        _batch_vs_single(device, which)
+    finally:
         api.set_split_maxn(-1)
 
 
-@pytest.mark.parametrize("which", ["mixed", "other_kinds"])
-def test_batch_matches_single_volume_and_oracle(device, which):
-    print("case batch", which, flush=True)
-    vols, pts, grads, cs = _mixed(device, specs=MIXED if which == "mixed" else OTHER_KINDS)
+def _batch_vs_single(device, which):
+    vols, pts, grads, cs = _mixed(device, specs=OTHER_KINDS if which == "other_kinds" else MIXED)
     plan = api.BatchPlan(vols, pts, grads, autotune=True)
     assert plan.tile in (1024, 4096, 16384) and plan.blocks >= 1
     val, grad = plan.run()
