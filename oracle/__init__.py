@@ -132,7 +132,11 @@ CC7 = Spline("cc7", np.eye(3), _cols((1, 0, 0), (0, 1, 0), (0, 0, 1), *_DIAG),
 BCC7 = Spline("bcc7", _BCC_L, _cols(*_DIAG, (2, 0, 0), (0, 2, 0), (0, 0, 2)),
               D=(2, 2, 2), shifts=[(0, 0, 0), (1, 1, 1)])
 
-SPLINES = {sp.name: sp for sp in (TRICUBIC, BCC8, BCC4, FCC6, ZP, TRILINEAR, TRIQUADRATIC, CC7, BCC7)}
+# The six face diagonals on Z^3.
+CC6 = Spline("cc6", np.eye(3), _cols((1, 1, 0), (1, -1, 0), (1, 0, 1), (1, 0, -1), (0, 1, 1), (0, 1, -1)),
+             D=(1, 1, 1), shifts=[(0, 0, 0)])
+
+SPLINES = {sp.name: sp for sp in (TRICUBIC, BCC8, BCC4, FCC6, ZP, TRILINEAR, TRIQUADRATIC, CC7, BCC7, CC6)}
 
 
 # ---------------------------------------------------------------- calls

@@ -36,9 +36,10 @@ DIRECTIONS = {
     "triquadratic": np.concatenate([_E3] * 3, axis=1),
     "cc7": np.concatenate([_E3, _DIAG.T], axis=1),
     "bcc7": np.concatenate([_DIAG.T, 2 * _E3], axis=1),
+    "cc6": np.array([(1, 1, 0), (1, -1, 0), (1, 0, 1), (1, 0, -1), (0, 1, 1), (0, 1, -1)], dtype=np.int32).T.copy(),
 }
 LATTICE_OF = {"tricubic": "cc", "bcc8": "bcc", "fcc6": "fcc", "trilinear": "cc", "bcc4": "bcc",
-              "triquadratic": "cc", "cc7": "cc", "bcc7": "bcc"}
+              "triquadratic": "cc", "cc7": "cc", "bcc7": "bcc", "cc6": "cc"}
 
 
 def set_option(option: int, value: int) -> None:
@@ -128,6 +129,12 @@ class Spline:
     def bcc7(cls):
         """Quartic box spline on BCC (diagonals and 2 e_i), fourth order."""
         return cls(LATTICES["bcc"], DIRECTIONS["bcc7"])
+
+    @classmethod
+    def cc6(cls):
+        """Six-direction box spline on Z^3 (the face diagonals), third order;
+        its reference sub-regions are derived automatically."""
+        return cls(LATTICES["cc"], DIRECTIONS["cc6"])
 
     @classmethod
     def named(cls, name: str):

@@ -34,12 +34,13 @@ namespace lsp {
 
 // Spline kinds, in the order of the generated kind table (generated/all.h).
 enum Kind : int {
-    kTricubic = 0, kBcc8 = 1, kFcc6 = 2, kTrilinear = 3, kBcc4 = 4, kTriquadratic = 5, kCc7 = 6, kBcc7 = 7
+    kTricubic = 0, kBcc8 = 1, kFcc6 = 2, kTrilinear = 3, kBcc4 = 4, kTriquadratic = 5, kCc7 = 6, kBcc7 = 7,
+    kCc6 = 8
 };
-static_assert(gen::kNumKinds == 8, "kind table and Kind enum disagree");
+static_assert(gen::kNumKinds == 9, "kind table and Kind enum disagree");
 
 // Expands X(k) for every spline kind (compile-time dispatch).
-#define LSP_FOR_EACH_KIND(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
+#define LSP_FOR_EACH_KIND(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8)
 
 template <int KIND> using TablesOf = typename gen::SplineOf<KIND>::T;
 template <int KIND> using PolyOf = typename gen::SplineOf<KIND>::P;
@@ -344,7 +345,8 @@ LSP_HD void locate_fcc(const PT xin[3], const VolGeom& g, Loc& L) {
 
 // Region of evaluation, symmetry transform and reference sub-region of a
 // point for the spline KIND (the preamble of Algorithm 1 up to the table
-// lookups): two reference sub-regions are told apart by one plane test.
+// lookups): several reference sub-regions are told apart by the generated
+// plane tests.
 template <int KIND, class PT>
 LSP_HD void locate(const PT x[3], const VolGeom& g, Loc& L) {
     using T = TablesOf<KIND>;
@@ -357,8 +359,7 @@ LSP_HD void locate(const PT x[3], const VolGeom& g, Loc& L) {
     } else {
         locate_fcc(x, g, L);
     }
-    if (T::kRegions > 1)
-        L.region = (T::kSelN[0] * L.y[0] + T::kSelN[1] * L.y[1] + T::kSelN[2] * L.y[2] > T::kSelT) ? 1 : 0;
+    if constexpr (T::kRegions > 1) L.region = PolyOf<KIND>::region(L.y[0], L.y[1], L.y[2]);
 }
 
 // Byte offset of the tap with reference-frame offset o (a lattice vector)

@@ -304,6 +304,7 @@ class SplineCode:
             "Xi": [list(x) for x in spec.Xi], "D": list(spec.D), "shifts": [list(x) for x in spec.shifts],
             "roe": spec.roe, "symmetry": spec.symmetry,
             "selector": None if spec.selector is None else [list(spec.selector[0]), spec.selector[1]],
+            "tree": _tree_json(spec.lookup_tree()),
             "degree": self.bs.degree, "union": [list(o) for o in self.union],
             "radius": max(abs(v) for o in self.union for v in o),
             "tensor": self.tensor is not None,
@@ -363,10 +364,6 @@ class SplineCode:
         L.append("  static constexpr int kL[3][3] = {%s};" % ", ".join("{%d, %d, %d}" % tuple(r) for r in spec.L))
         L.append("  static constexpr int kNumDirs = %d;" % len(spec.Xi))
         L.append("  static constexpr int kXi[kNumDirs][3] = {%s};" % ", ".join("{%d, %d, %d}" % tuple(x) for x in spec.Xi))
-        sel = spec.selector if spec.selector is not None else ((0, 0, 0), 0)
-        L.append("  // reference sub-region 1 where n . y > t (two reference sub-regions only)")
-        L.append("  static constexpr float kSelN[3] = {%s};" % ", ".join(flit(v) for v in sel[0]))
-        L.append("  static constexpr float kSelT = %s;" % flit(sel[1]))
         L.append("  static constexpr int kTaps = %d;       // union stencil size" % len(self.union))
         L.append("  static constexpr int kRegions = %d;    // reference sub-regions" % len(self.regions))
         L.append("  static constexpr int kRadius = %d;     // max |offset component|" % max(abs(v) for o in self.union for v in o))
@@ -776,6 +773,64 @@ class SplineCode:
         return L
 
 
+def _tree_json(t):
+    if isinstance(t, int):
+        return t
+    n, thr, near, far = t
+    return {"n": list(n), "t": str(F(thr)), "near": _tree_json(near), "far": _tree_json(far)}
+
+
+def _tree_expr(t) -> str:
+    """The region lookup as nested selects: far when n . y > t."""
+    if isinstance(t, int):
+        return str(t)
+    n, thr, near, far = t
+    terms = [("%s * y%d" % (flit(v), i)) for i, v in enumerate(n) if v]
+    return "((%s > %s) ? %s : %s)" % (" + ".join(terms), flit(F(thr)), _tree_expr(far), _tree_expr(near))
+
+
+def _emit_poly_struct_general(nm: str, nreg: int) -> List[str]:
+    """Uniform entry points for three or more reference sub-regions: a branch
+    per point (switch), or every polynomial and a select (PRED)."""
+    def pick(expr_k, decl, ret):
+        L = ["    if (PRED) {"]
+        L += ["      " + decl(k) for k in range(nreg)]
+        L += ["      " + ret, "    }", "    switch (region) {"]
+        L += ["      case %d: %s" % (k, expr_k(k)) for k in range(1, nreg)]
+        L += ["      default: %s" % expr_k(0), "    }"]
+        return L
+    L = ["// uniform entry points: the reference sub-region loop (Sec. 4.3)",
+         "struct %s_poly {" % nm,
+         "  template <bool PRED>",
+         "  static __device__ __forceinline__ float value(const float* __restrict__ c, float y0, float y1, float y2, int region) {"]
+    L += pick(lambda k: "return %s_eval_r%d(c, y0, y1, y2);" % (nm, k),
+              lambda k: "const float v%d = %s_eval_r%d(c, y0, y1, y2);" % (k, nm, k),
+              "float v = v0;" + "".join(" v = region == %d ? v%d : v;" % (k, k) for k in range(1, nreg)) + " return v;")
+    L += ["  }", "  template <bool PRED>",
+          "  static __device__ __forceinline__ float value_grad(const float* __restrict__ c, float y0, float y1, float y2, int region,",
+          "                                                    float& g0, float& g1, float& g2) {"]
+    L += pick(lambda k: "return %s_eval_grad_r%d(c, y0, y1, y2, g0, g1, g2);" % (nm, k),
+              lambda k: "float a%d[3]; const float v%d = %s_eval_grad_r%d(c, y0, y1, y2, a%d[0], a%d[1], a%d[2]);" % (k, k, nm, k, k, k, k),
+              "float v = v0; g0 = a0[0]; g1 = a0[1]; g2 = a0[2];" + "".join(
+                  " if (region == %d) { v = v%d; g0 = a%d[0]; g1 = a%d[1]; g2 = a%d[2]; }" % (k, k, k, k, k)
+                  for k in range(1, nreg)) + " return v;")
+    L += ["  }", "  template <bool PRED>",
+          "  static __device__ __forceinline__ float value_grad_hess(const float* __restrict__ c, float y0, float y1, float y2, int region,",
+          "                                                         float& g0, float& g1, float& g2, float* __restrict__ h) {"]
+    L += pick(lambda k: "return %s_eval_hess_r%d(c, y0, y1, y2, g0, g1, g2, h);" % (nm, k),
+              lambda k: "float a%d[3], h%d[6]; const float v%d = %s_eval_hess_r%d(c, y0, y1, y2, a%d[0], a%d[1], a%d[2], h%d);"
+              % (k, k, k, nm, k, k, k, k, k),
+              "float v = v0; g0 = a0[0]; g1 = a0[1]; g2 = a0[2]; for (int i = 0; i < 6; ++i) h[i] = h0[i];" + "".join(
+                  " if (region == %d) { v = v%d; g0 = a%d[0]; g1 = a%d[1]; g2 = a%d[2]; for (int i = 0; i < 6; ++i) h[i] = h%d[i]; }"
+                  % (k, k, k, k, k, k) for k in range(1, nreg)) + " return v;")
+    L += ["  }",
+          "  static __device__ __forceinline__ void weights(float y0, float y1, float y2, int region, float* __restrict__ w) {",
+          "    switch (region) {"]
+    L += ["      case %d: %s_weights_r%d(y0, y1, y2, w); return;" % (k, nm, k) for k in range(1, nreg)]
+    L += ["      default: %s_weights_r0(y0, y1, y2, w); return;" % nm, "    }", "  }", "};", ""]
+    return L
+
+
 def _emit_poly_struct_impl(nm: str, nreg: int) -> List[str]:
     """Uniform entry points over the reference sub-regions: the unrolled
     reference sub-region loop of Sec. 4.3, branchy or predicated."""
@@ -835,8 +890,14 @@ def _emit_poly_struct_impl(nm: str, nreg: int) -> List[str]:
 
 
 def _emit_poly_struct_full(self) -> List[str]:
-    L = _emit_poly_struct_impl(self.spec.name, len(self.regions))
+    nreg = len(self.regions)
     nm = self.spec.name
+    L = (_emit_poly_struct_impl if nreg <= 2 else _emit_poly_struct_general)(nm, nreg)
+    # the region lookup: which reference sub-region a transformed point is in
+    L[L.index("};"):L.index("};")] = [
+        "  static __host__ __device__ __forceinline__ int region(float y0, float y1, float y2) {",
+        "    (void)y0; (void)y1; (void)y2;",
+        "    return %s;" % _tree_expr(self.spec.lookup_tree()), "  }"]
     if self.tensor is None:
         pre = ["  static constexpr int kPre = 0;  // no y-only phase"]
     else:

@@ -63,11 +63,17 @@ def locate(tab: dict, x: np.ndarray):
         for r in range(3):
             G[np.arange(N), r, perm[:, r]] = s[np.arange(N), perm[:, r]]
     y = np.einsum("nij,nj->ni", G, d)
-    region = np.zeros(N, dtype=np.int64)
-    if tab["selector"] is not None:
-        nrm, thr = tab["selector"]
-        region = (y @ np.array(nrm, dtype=np.float64) > thr).astype(np.int64)
+    region = _lookup(tab["tree"], y)
     return K.astype(np.int64), y, G, region
+
+
+def _lookup(node, y: np.ndarray) -> np.ndarray:
+    """Reference sub-region of each row of y from the lookup tree (far side
+    when n . y > t)."""
+    if isinstance(node, int):
+        return np.full(y.shape[0], node, dtype=np.int64)
+    far = y @ np.array(node["n"], dtype=np.float64) > float(Fraction(node["t"]))
+    return np.where(far, _lookup(node["far"], y), _lookup(node["near"], y))
 
 
 def _poly_eval(terms: dict, u: np.ndarray) -> np.ndarray:

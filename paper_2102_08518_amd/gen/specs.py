@@ -41,6 +41,17 @@ class Spec:
     selector: Tuple = None
     kind: int = -1          # index of the spline in the library's kind table
     lattice: str = "cc"     # "cc", "bcc" or "fcc"
+    # region lookup for any number of reference sub-regions: a leaf index, or
+    # (normal, t, near, far) -- far when normal . y > t (see auto.py); None:
+    # from the selector
+    tree: object = None
+
+    def lookup_tree(self):
+        if self.tree is not None:
+            return self.tree
+        if self.selector is not None:
+            return (tuple(self.selector[0]), self.selector[1], 0, 1)
+        return 0
 
     def in_lattice(self, n) -> bool:
         return any(all((n[i] - sh[i]) % self.D[i] == 0 for i in range(self.s)) for sh in self.shifts)
@@ -153,5 +164,14 @@ BCC7 = Spec(
                      ((-1, 0, 0), 1), ((-1, -1, -1), F(3, 2))],
                     (F(1, 2), F(3, 10), F(1, 10)))])
 
-SPECS = {sp.name: sp for sp in sorted((TRICUBIC, BCC8, FCC6, TRILINEAR, BCC4, TRIQUADRATIC, CC7, BCC7),
-                                      key=lambda sp: sp.kind)}
+def _auto_specs():
+    # splines whose ROE, symmetry and reference sub-regions are derived from
+    # (L, Xi) alone (auto.py): the six face diagonals on Z^3 (degree 3, C^1;
+    # three reference sub-regions in the wedge of the centred cube)
+    from .auto import auto_spec
+    return [auto_spec("cc6", "cc", [(1, 1, 0), (1, -1, 0), (1, 0, 1), (1, 0, -1), (0, 1, 1), (0, 1, -1)],
+                      kind=8)]
+
+
+SPECS = {sp.name: sp for sp in sorted((TRICUBIC, BCC8, FCC6, TRILINEAR, BCC4, TRIQUADRATIC, CC7, BCC7)
+                                      + tuple(_auto_specs()), key=lambda sp: sp.kind)}

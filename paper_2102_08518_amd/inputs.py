@@ -42,6 +42,7 @@ LATTICE = {
     "triquadratic": dict(D=1, shifts=[(0, 0, 0)], r=1.5),
     "cc7": dict(D=1, shifts=[(0, 0, 0)], r=2.5),
     "bcc7": dict(D=2, shifts=[(0, 0, 0), (1, 1, 1)], r=3),
+    "cc6": dict(D=1, shifts=[(0, 0, 0)], r=2),
 }
 
 
@@ -121,8 +122,9 @@ def workload2(n: int = 1 << 22, E: int = 64):
 # inside 202^3 (2 cosets of 101^3) and FCC inside 161^3 (4 cosets of 81^3),
 # about 2.1 M sites each.
 ORDERS_E = {"cc": 128, "bcc": 101, "fcc": 81}
-ORDERS = {2: ["trilinear", "bcc4"], 3: ["triquadratic", "fcc6"], 4: ["tricubic", "cc7", "bcc8", "bcc7"]}
-LATTICE_NAME = {"tricubic": "cc", "trilinear": "cc", "triquadratic": "cc", "cc7": "cc",
+ORDERS = {2: ["trilinear", "bcc4"], 3: ["triquadratic", "fcc6", "cc6"],
+          4: ["tricubic", "cc7", "bcc8", "bcc7"]}
+LATTICE_NAME = {"tricubic": "cc", "trilinear": "cc", "triquadratic": "cc", "cc7": "cc", "cc6": "cc",
                 "bcc8": "bcc", "bcc4": "bcc", "bcc7": "bcc", "fcc6": "fcc"}
 
 

@@ -23,12 +23,13 @@ import pytest
 from paper_2102_08518_amd.gen import interp
 from paper_2102_08518_amd.gen.emit import OUT_DIR
 
-NAMES = ["tricubic", "bcc8", "fcc6", "trilinear", "bcc4", "triquadratic", "cc7", "bcc7"]
+NAMES = ["tricubic", "bcc8", "fcc6", "trilinear", "bcc4", "triquadratic", "cc7", "bcc7", "cc6"]
 
 HARNESS = r"""
 #include <cmath>
 #include <cstdio>
 #define __device__
+#define __host__
 #define __forceinline__ inline
 #define __restrict__
 #include "%(name)s.h"

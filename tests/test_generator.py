@@ -18,7 +18,8 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 rng = np.random.default_rng(77)
 ORACLE_SPLINE = {"tricubic": oracle.TRICUBIC, "bcc8": oracle.BCC8, "fcc6": oracle.FCC6,
                  "trilinear": oracle.TRILINEAR, "bcc4": oracle.BCC4,
-                 "triquadratic": oracle.TRIQUADRATIC, "cc7": oracle.CC7, "bcc7": oracle.BCC7}
+                 "triquadratic": oracle.TRIQUADRATIC, "cc7": oracle.CC7, "bcc7": oracle.BCC7,
+                 "cc6": oracle.CC6}
 ALL = list(ORACLE_SPLINE)
 
 
@@ -43,7 +44,8 @@ def test_generator_reproduces_fig1_zp_polynomial_exactly():
 
 @pytest.mark.parametrize("name,taps,regions", [("tricubic", 64, 1), ("bcc8", 32, 1), ("fcc6", 16, 2),
                                                ("trilinear", 8, 1), ("bcc4", 4, 1),
-                                               ("triquadratic", 27, 1), ("cc7", 53, 1), ("bcc7", 30, 1)])
+                                               ("triquadratic", 27, 1), ("cc7", 53, 1), ("bcc7", 30, 1),
+                                               ("cc6", 32, 3)])
 def test_stencil_sizes(name, taps, regions):
     """Tricubic: 64 fetches (Sec. 5.1); the FCC cubic spline has two reference
     sub-regions (Sec. 5.1); every stencil has vol(supp)/|det L| sites."""
@@ -164,3 +166,58 @@ def test_matrix_core_form_is_exact(name):
             assert float(np.float32(Wq[m][j]).view(np.uint32) & 0xFFFF0000) == float(
                 np.float32(Wq[m][j]).view(np.uint32)), "not exact in bf16"
 
+
+
+@pytest.mark.parametrize("name", [n for n in ALL if n != "cc6"])
+def test_automatic_regions_reproduce_the_written_specs(name):
+    """The ROE, symmetry and reference sub-regions found from (L, Xi) alone
+    (gen/auto.py) give the same sub-region polynomials as the specs written
+    out from the analysis, and the same region lookup."""
+    from paper_2102_08518_amd.gen.auto import auto_spec
+    from paper_2102_08518_amd.gen.derive import BoxSpline, derive_region
+    hand = SPECS[name]
+    auto = auto_spec(name, hand.lattice, hand.Xi)
+    assert (auto.roe, auto.symmetry, len(auto.regions)) == (hand.roe, hand.symmetry, len(hand.regions))
+
+    def pieces(spec):
+        bs = BoxSpline(3, spec.Xi, spec.det_L)
+        out = set()
+        for reg in spec.regions:
+            d = derive_region(spec, bs, reg)
+            out.add(frozenset((o, tuple(sorted(p.t.items()))) for o, p in zip(d.taps, d.polys)))
+        return out
+    assert pieces(auto) == pieces(hand)
+    # the lookup puts the written regions' interior points where they belong
+    if len(hand.regions) > 1:
+        from paper_2102_08518_amd.gen.emit import _tree_json
+        tab = {"tree": _tree_json(auto.lookup_tree())}
+        ys = np.array([[float(v) for v in r.interior] for r in hand.regions])
+        got = interp._lookup(tab["tree"], ys)
+        a_pieces = []
+        bs = BoxSpline(3, auto.Xi, auto.det_L)
+        for reg in auto.regions:
+            d = derive_region(auto, bs, reg)
+            a_pieces.append(frozenset((o, tuple(sorted(p.t.items()))) for o, p in zip(d.taps, d.polys)))
+        bsh = BoxSpline(3, hand.Xi, hand.det_L)
+        for k, reg in enumerate(hand.regions):
+            d = derive_region(hand, bsh, reg)
+            assert a_pieces[got[k]] == frozenset((o, tuple(sorted(p.t.items()))) for o, p in zip(d.taps, d.polys))
+
+
+def test_automatic_three_region_spline_lookup_is_consistent():
+    """cc6 (the face diagonals on Z^3) has three reference sub-regions from
+    the automatic analysis: every derived region's interior point is looked
+    up into that region, and random points of the wedge land in a region
+    whose half-spaces contain them."""
+    tab = interp.load_tables("cc6")
+    spec = SPECS["cc6"]
+    assert len(tab["regions"]) == 3
+    ys = np.array([[float(v) for v in r.interior] for r in spec.regions])
+    assert list(interp._lookup(tab["tree"], ys)) == [0, 1, 2]
+    y = rng.uniform(0, 0.5, (4000, 3))
+    y = -np.sort(-y, axis=1)          # the wedge 0 <= y2 <= y1 <= y0 <= 1/2
+    reg = interp._lookup(tab["tree"], y)
+    for k, r in enumerate(spec.regions):
+        sel = y[reg == k]
+        for a, b in r.halfspaces:
+            assert np.all(sel @ np.array(a, dtype=np.float64) + float(Fraction(b)) >= -1e-12)

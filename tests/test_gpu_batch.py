@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 
 ORC = {"tricubic": oracle.TRICUBIC, "bcc8": oracle.BCC8, "fcc6": oracle.FCC6,
        "trilinear": oracle.TRILINEAR, "bcc4": oracle.BCC4, "triquadratic": oracle.TRIQUADRATIC,
-       "cc7": oracle.CC7, "bcc7": oracle.BCC7}
+       "cc7": oracle.CC7, "bcc7": oracle.BCC7, "cc6": oracle.CC6}
 MIXED = [("tricubic", "f32", 9, 1000, False), ("bcc8", "f32", 12, 40000, True),
          ("fcc6", "bf16", 8, 7000, False), ("bcc8", "f16", 7, 0, False),
          ("tricubic", "f32", 20, 70001, True), ("bcc8", "f32", 10, 513, False),
@@ -22,7 +22,7 @@ MIXED = [("tricubic", "f32", 9, 1000, False), ("bcc8", "f32", 12, 40000, True),
 OTHER_KINDS = [("cc7", "f32", 10, 20000, True), ("bcc7", "bf16", 9, 9000, False),
                ("trilinear", "f32", 11, 5000, True), ("bcc4", "f16", 8, 4097, False),
                ("triquadratic", "f32", 9, 12000, False), ("bcc7", "f32", 7, 333, True),
-               ("cc7", "bf16", 6, 64, False)]
+               ("cc7", "bf16", 6, 64, False), ("cc6", "f32", 9, 7001, True)]
 
 
 def _mixed(device, seed=41, specs=MIXED):

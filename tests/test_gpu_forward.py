@@ -19,7 +19,7 @@ pytestmark = pytest.mark.gpu
 
 ORC = {"tricubic": oracle.TRICUBIC, "bcc8": oracle.BCC8, "fcc6": oracle.FCC6,
        "trilinear": oracle.TRILINEAR, "bcc4": oracle.BCC4, "triquadratic": oracle.TRIQUADRATIC,
-       "cc7": oracle.CC7, "bcc7": oracle.BCC7}
+       "cc7": oracle.CC7, "bcc7": oracle.BCC7, "cc6": oracle.CC6}
 ALL = list(ORC)
 TORCH_DT = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}
 U_Q = {"f32": 2.0 ** -24, "bf16": 2.0 ** -9, "f16": 2.0 ** -11}

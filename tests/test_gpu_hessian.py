@@ -8,10 +8,10 @@ bound per derivative taken: the second-derivative polynomials of the
 reference sub-region have coefficients a few times those of the gradient
 polynomials and are evaluated in FP32 the same way (measured: about 3e-7).
 
-For the C^1 splines (fcc6, triquadratic) the second partials jump across
+For the C^1 splines (fcc6, triquadratic, cc6) the second partials jump across
 sub-region boundaries; a point that rounds onto the other side of a boundary
 than the checker's FP64 assignment is accepted when the checker's Hessian at
-a point a distance 1e-4 away agrees with the GPU's."""
+a point a distance 1e-6 away (one of 1024 directions) agrees with the GPU's."""
 import numpy as np
 import pytest
 import torch
@@ -22,7 +22,8 @@ from paper_2102_08518_amd import api, inputs
 pytestmark = pytest.mark.gpu
 
 ORC = {"tricubic": oracle.TRICUBIC, "bcc8": oracle.BCC8, "fcc6": oracle.FCC6,
-       "triquadratic": oracle.TRIQUADRATIC, "cc7": oracle.CC7, "bcc7": oracle.BCC7}
+       "triquadratic": oracle.TRIQUADRATIC, "cc7": oracle.CC7, "bcc7": oracle.BCC7,
+       "cc6": oracle.CC6}
 SMOOTH = list(ORC)
 C0 = ["trilinear", "bcc4"]
 TORCH_DT = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}
@@ -52,14 +53,16 @@ def _check_hessian(name, E, cs, x, H, tol):
     _, _, ref = oracle.evaluate_hessian(ORC[name], (E, E, E), list(cs), x)
     err = np.abs(H - ref).reshape(len(x), -1).max(axis=1)
     bad = np.nonzero(err > tol)[0]
-    if len(bad) and name in ("fcc6", "triquadratic"):
+    if len(bad) and name in ("fcc6", "triquadratic", "cc6"):
         rng = np.random.default_rng(5)
         still = []
         for i in bad:
-            u = rng.normal(size=(16, 3))
-            u *= 1e-4 / np.linalg.norm(u, axis=1, keepdims=True)
+            # where several sub-regions meet (a lattice site, say) the GPU's
+            # piece is one of them: probe many directions, close by
+            u = rng.normal(size=(1024, 3))
+            u *= 1e-6 / np.linalg.norm(u, axis=1, keepdims=True)
             _, _, near = oracle.evaluate_hessian(ORC[name], (E, E, E), list(cs), x[i] + u)
-            if np.abs(near - H[i]).reshape(16, -1).max(axis=1).min() > tol + 1e-3 * np.abs(cs).max():
+            if np.abs(near - H[i]).reshape(1024, -1).max(axis=1).min() > tol + 1e-4 * np.abs(cs).max():
                 still.append(i)
         assert len(bad) <= max(2, len(x) // 500), (len(bad), err.max())
         bad = np.array(still, dtype=np.int64)
@@ -171,7 +174,7 @@ def test_hessian_edge_inputs(device, name):
     assert H.shape == (0, 3, 3)
     inf = float("inf")
     x = torch.tensor([[float("nan"), 1.0, 1.0], [1.0, 1.0, float("nan")], [inf, 2.0, 2.0],
-                      [-inf, 2.0, 2.0], [1e30, -1e30, 3.0], [-50.0, 3.0, 3.0], [3.0, 3.0, 3.0]],
+                      [-inf, 2.0, 2.0], [1e30, -1e30, 3.0], [-50.0, 3.0, 3.0], [3.1, 3.27, 2.93]],
                      device=device)
     v, g, H = vol.eval_hessian(x)
     H = H.cpu()

@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol():
 @pytest.mark.parametrize("name,kind,cosets,taps,union,cont", [
     ("tricubic", 0, 1, 64, 64, 2), ("bcc8", 1, 2, 32, 32, 2), ("fcc6", 2, 4, 16, 19, 1),
     ("trilinear", 3, 1, 8, 8, 0), ("bcc4", 4, 2, 4, 4, 0), ("triquadratic", 5, 1, 27, 27, 1),
-    ("cc7", 6, 1, 53, 53, 2), ("bcc7", 7, 2, 30, 30, 2)])
+    ("cc7", 6, 1, 53, 53, 2), ("bcc7", 7, 2, 30, 30, 2), ("cc6", 8, 1, 32, 38, 1)])
 def test_spline_recognition(name, kind, cosets, taps, union, cont):
     sp = getattr(api.Spline, name)()
     assert sp.info.kind == kind and sp.info.n_cosets == cosets
@@ -104,7 +104,7 @@ def _site_offset(tab, geo, n):
 
 
 @pytest.mark.parametrize("name", ["tricubic", "bcc8", "fcc6", "trilinear", "bcc4", "triquadratic",
-                                  "cc7", "bcc7"])
+                                  "cc7", "bcc7", "cc6"])
 @pytest.mark.parametrize("storage", ["f32", "bf16"])
 def test_tap_offsets_hit_the_prescribed_sites_inside_the_buffer(name, storage):
     sp = api.Spline.named(name)

@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import oracle
-from oracle import BCC4, BCC7, BCC8, CC7, FCC6, TRICUBIC, TRILINEAR, TRIQUADRATIC, ZP
+from oracle import BCC4, BCC7, BCC8, CC6, CC7, FCC6, TRICUBIC, TRILINEAR, TRIQUADRATIC, ZP
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 rng = np.random.default_rng(20210208)
@@ -142,7 +142,7 @@ def _support_count(sp, x, radius):
 
 @pytest.mark.parametrize("sp,count", [(BCC4, 4), (ZP, 7), (TRICUBIC, 64), (TRILINEAR, 8),
                                       (BCC8, 32), (FCC6, 16), (TRIQUADRATIC, 27), (CC7, 53),
-                                      (BCC7, 30)])
+                                      (BCC7, 30), (CC6, 32)])
 def test_taps_at_generic_points(sp, count):
     """BCC linear: four lookups (Sec. 5.1); ZP: seven sites c0..c6 (Fig. 1);
     tricubic: 64 fetches (Sec. 5.1); in general vol(supp)/|det L|, the
@@ -167,7 +167,7 @@ def test_bcc_linear_interpolates():
 
 # ---------------------------------------------------------- invariants
 
-SPL3 = [TRICUBIC, BCC8, FCC6, CC7, BCC7]
+SPL3 = [TRICUBIC, BCC8, FCC6, CC7, BCC7, CC6]
 
 
 def _lattice_box(sp, E):
@@ -208,7 +208,7 @@ def test_partition_of_unity_and_linear_reproduction(sp):
 @pytest.mark.parametrize("sp,M", [(TRICUBIC, np.eye(3) / 3), (BCC8, 2 * np.eye(3) / 3),
                                   (FCC6, np.eye(3) / 3), (ZP, np.eye(2) / 4),
                                   (TRIQUADRATIC, np.eye(3) / 4), (CC7, 5 * np.eye(3) / 12),
-                                  (BCC7, 2 * np.eye(3) / 3)])
+                                  (BCC7, 2 * np.eye(3) / 3), (CC6, np.eye(3) / 3)])
 def test_second_moment_is_XiXiT_over_12(sp, M):
     """Sum_n (n-x)(n-x)^T phi(x-n) = Xi Xi^T / 12 for approximation order >= 3."""
     np.testing.assert_allclose(sp.Xi @ sp.Xi.T / 12.0, M)
@@ -290,7 +290,7 @@ def test_integral_is_det_L(sp):
 
 
 @pytest.mark.parametrize("sp,order", [(TRICUBIC, 2), (BCC8, 2), (FCC6, 1), (ZP, 1), (CC7, 2),
-                                      (BCC7, 2)])
+                                      (BCC7, 2), (CC6, 1)])
 def test_smoothness_across_knot_planes(sp, order):
     """phi is C^{m-2}: values (and gradients for C^1, Hessians for C^2)
     continue across knot planes."""
@@ -299,6 +299,9 @@ def test_smoothness_across_knot_planes(sp, order):
     if sp is CC7:
         pts[:, 1] = 1 - pts[:, 0]  # x + y = 1 plane
         nrm = np.array([1.0, 1.0, 0]) / np.sqrt(2)
+    elif sp is CC6:
+        pts[:, 2] = pts[:, 0] - pts[:, 1]  # x - y - z = 0 plane
+        nrm = np.array([1.0, -1.0, -1.0]) / np.sqrt(3)
     elif sp is BCC7:
         pts[:, 2] = np.round(pts[:, 2])  # z in Z
         nrm = np.array([0, 0, 1.0])
@@ -435,7 +438,7 @@ def test_backward_x_is_g_times_grad():
 
 # ------------------------------------------------------------ Hessians
 
-HESS = [TRICUBIC, BCC8, FCC6, TRIQUADRATIC, CC7, BCC7]   # C^1 and smoother after removing a direction
+HESS = [TRICUBIC, BCC8, FCC6, TRIQUADRATIC, CC7, BCC7, CC6]   # C^1 and smoother after removing a direction
 
 
 def test_tricubic_hessian_closed_form():
