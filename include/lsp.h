@@ -78,7 +78,8 @@ typedef struct lsp_spline_info {
     int s;                 /* dimension (3) */
     int kind;              /* 0 tricubic on Z^3, 1 BCC 8-direction, 2 FCC 6-direction,
                               3 trilinear, 4 BCC linear (4-direction), 5 triquadratic,
-                              6 Z^3 7-direction, 7 BCC quartic (7-direction) */
+                              6 Z^3 7-direction, 7 BCC quartic (7-direction),
+                              8 Z^3 face diagonals (6-direction) */
     int n_cosets;          /* Cartesian cosets of the lattice */
     int D[3];              /* coset scale */
     int shift[4][3];       /* coset shifts (first n_cosets rows used) */
@@ -153,8 +154,8 @@ lsp_status lsp_set_option(int option, int value);
  * [I, the four diagonals (+-1,+-1,+-1)] (7-direction, fourth order); the BCC
  * lattice with its four diagonals once (linear), twice (8-direction) or with
  * 2I (quartic, 7-direction); the FCC lattice with the six directions
- * (1,+-1,0), (1,0,+-1), (0,1,+-1).  Anything else returns
- * LSP_E_UNSUPPORTED.  Host only; touches no device.
+ * (1,+-1,0), (1,0,+-1), (0,1,+-1); Z^3 with the same six face diagonals.
+ * Anything else returns LSP_E_UNSUPPORTED.  Host only; touches no device.
  */
 lsp_status lsp_spline_create(int s, const int32_t* L, const int32_t* Xi, int n_dirs,
                              lsp_spline** out);

@@ -416,8 +416,8 @@ lsp_status lsp_spline_create(int s, const int32_t* L, const int32_t* Xi, int n_d
     }
     return fail(LSP_E_UNSUPPORTED,
                 "no generated code for this (L, Xi): supported are the trilinear, triquadratic, "
-                "tricubic and 7-direction box splines on Z^3, the BCC 4-, 7- and 8-direction "
-                "and the FCC 6-direction box splines");
+                "tricubic, 6-direction and 7-direction box splines on Z^3, the BCC 4-, 7- and "
+                "8-direction and the FCC 6-direction box splines");
 }
 
 void lsp_spline_destroy(lsp_spline* sp) { delete sp; }
