@@ -308,7 +308,12 @@ def main():
             "algorithmic_flops_per_point": 2 * fma,
             "frac_of_nonpacked_peak": round(achieved / PEAK_FP32_NONPACKED_TFLOPS, 4),
             "hbm_compulsory_GBs": round(16.0 * n / t_k / 1e9, 1),
-            "hbm_compulsory_frac": round(16.0 * n / t_k / 1e9 / PEAK_HBM_GBS, 4)}
+            "hbm_compulsory_frac": round(16.0 * n / t_k / 1e9 / PEAK_HBM_GBS, 4),
+            # the bytes a fetch of every tap would move (point, value and 4 B
+            # per tap), against the HBM peak; served mostly by L1/L2, not HBM
+            "effective_gather_bytes_per_point": 16 + 4 * sp.info.taps,
+            "effective_gather_GBs": round((16 + 4 * sp.info.taps) * n / t_k / 1e9, 1),
+            "effective_gather_frac_of_hbm_peak": round((16 + 4 * sp.info.taps) * n / t_k / 1e9 / PEAK_HBM_GBS, 4)}
 
     cpu = None
     if not args.no_cpu:
