@@ -159,6 +159,23 @@ lsp_status lsp_set_option(int option, int value);
  */
 lsp_status lsp_spline_create(int s, const int32_t* L, const int32_t* Xi, int n_dirs,
                              lsp_spline** out);
+
+/*
+ * A spline compiled at run time (the analogue of the paper's just-in-time
+ * code generation, Sec. 3.3): `path` names a shared library built from the
+ * generated code of one (L, Xi) pair together with this library's kernel
+ * headers (paper_2102_08518_amd.jit builds them).  It must export
+ * lsp_plugin_describe and lsp_plugin_eval of the same library version.  The
+ * plugin stays loaded until the process ends.  Volumes of such a spline
+ * support lsp_volume_*, lsp_eval, lsp_eval_grad, lsp_eval_hessian and the
+ * dL/dx of lsp_backward; the binned order, dL/dc and batch plans return
+ * LSP_E_UNSUPPORTED.  Host only.
+ *   path    host, NUL-terminated file name.
+ *   out     receives a handle owned by the caller (lsp_spline_destroy).
+ * Returns LSP_E_UNSUPPORTED if the file cannot be loaded, lacks the entry
+ * points or was built for another version.
+ */
+lsp_status lsp_spline_load_plugin(const char* path, lsp_spline** out);
 void lsp_spline_destroy(lsp_spline* sp);
 /* Fill `out` (host) with the spline's description.  Host only. */
 lsp_status lsp_spline_get_info(const lsp_spline* sp, lsp_spline_info* out);

@@ -19,6 +19,7 @@ STATUS = {0: "LSP_OK", 1: "LSP_E_INVALID_ARG", 2: "LSP_E_UNSUPPORTED", 3: "LSP_E
 
 # Every symbol include/lsp.h declares.
 EXPORTS = ("lsp_status_string", "lsp_last_error", "lsp_version", "lsp_set_option", "lsp_spline_create",
+           "lsp_spline_load_plugin",
            "lsp_spline_destroy", "lsp_spline_get_info", "lsp_volume_create", "lsp_volume_destroy",
            "lsp_volume_info", "lsp_volume_set_coeffs", "lsp_eval", "lsp_eval_grad",
            "lsp_eval_hessian", "lsp_eval_binned_workspace_size", "lsp_eval_binned",
@@ -70,6 +71,7 @@ def lib():
             "lsp_last_error": (ctypes.c_char_p, []),
             "lsp_version": (ctypes.c_char_p, []),
             "lsp_set_option": (ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
+            "lsp_spline_load_plugin": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(vp)]),
             "lsp_spline_create": (ctypes.c_int, [ctypes.c_int, i32p, i32p, ctypes.c_int,
                                                  ctypes.POINTER(vp)]),
             "lsp_spline_destroy": (None, [vp]),

@@ -5,6 +5,7 @@ library (liblsp.so).  Names follow the C ABI in include/lsp.h.
 from __future__ import annotations
 
 import ctypes
+import os
 from typing import Optional, Sequence
 
 import numpy as np
@@ -139,6 +140,25 @@ class Spline:
     @classmethod
     def named(cls, name: str):
         return cls(LATTICES[LATTICE_OF[name]], DIRECTIONS[name])
+
+    @classmethod
+    def from_plugin(cls, path: str):
+        """A spline compiled at run time (lsp_spline_load_plugin); see jit.py."""
+        obj = cls.__new__(cls)
+        h = ctypes.c_void_p()
+        N.check(N.lib().lsp_spline_load_plugin(os.fsencode(path), ctypes.byref(h)))
+        obj._h = h
+        info = N.SplineInfo()
+        N.check(N.lib().lsp_spline_get_info(h, ctypes.byref(info)))
+        obj.info = info
+        return obj
+
+    @classmethod
+    def compile(cls, lattice: str, Xi, name: Optional[str] = None):
+        """Analyse, generate and compile the box spline with directions Xi (the
+        rows) on lattice "cc", "bcc" or "fcc" at run time, then load it."""
+        from . import jit
+        return cls.from_plugin(jit.compile_spline(lattice, [tuple(int(v) for v in d) for d in Xi], name))
 
     @property
     def n_cosets(self) -> int:

@@ -1,5 +1,6 @@
 // Host side of the C ABI declared in include/lsp.h: spline recognition,
 // argument validation, volume storage and kernel dispatch.
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
 
 #include <stdarg.h>
@@ -20,6 +21,7 @@
 #include "lsp_backward.h"
 #include "lsp_batch.h"
 #include "lsp_binned.h"
+#include "lsp_plugin.h"
 #include "generated/all.h"
 
 namespace {
@@ -74,10 +76,14 @@ bool same_lattice(const i64 L[3][3], const i64 R[3][3]) {
     return true;
 }
 
+// Launch of the evaluation kernels of a spline compiled into a plugin.
+using PluginEval = hipError_t (*)(const lsp::EvalArgs*);
+
 struct SplineDef {
     int kind;
     int lattice;                 // 0 Z^3, 1 BCC, 2 FCC
-    const char* name;
+    std::string name;
+    PluginEval plugin_eval;      // null for the built-in splines
     i64 L[3][3];                 // columns are generators
     std::vector<std::vector<int>> dirs;  // canonical directions, with repeats
     int n_cosets;
@@ -134,43 +140,43 @@ std::vector<int> canon_dir(std::vector<int> d) {
     return d;
 }
 
-// The host description of spline KIND, read from its generated tables.
-template <int K>
-SplineDef make_def() {
-    using T = lsp::TablesOf<K>;
+// The host description of a spline, from the description of its generated
+// tables (lsp_plugin.h): built-in kinds and plugins alike.
+SplineDef def_from_desc(const lsp::SplineDesc& d) {
     SplineDef s{};
-    s.kind = K;
-    s.lattice = T::kLattice;
-    s.name = lsp::gen::SplineOf<K>::kName;
+    s.kind = d.kind;
+    s.lattice = d.lattice;
+    s.name = std::string(d.name, strnlen(d.name, sizeof(d.name)));
     for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) s.L[i][j] = T::kL[i][j];
-    for (int d = 0; d < T::kNumDirs; ++d)
-        s.dirs.push_back(canon_dir({T::kXi[d][0], T::kXi[d][1], T::kXi[d][2]}));
-    s.n_cosets = T::kNumCosets;
-    s.D = T::kD;
+        for (int j = 0; j < 3; ++j) s.L[i][j] = d.L[i][j];
+    for (int k = 0; k < d.n_dirs; ++k)
+        s.dirs.push_back(canon_dir({d.dirs[k][0], d.dirs[k][1], d.dirs[k][2]}));
+    s.n_cosets = d.n_cosets;
+    s.D = d.D;
     for (int m = 0; m < 4; ++m)
-        for (int a = 0; a < 3; ++a) s.shift[m][a] = T::kShift[m][a];
-    s.union_taps = T::kTaps;
-    s.taps = __builtin_popcountll(T::kRegionMask0);
-    s.n_reference = T::kRegions;
-    s.degree = T::kDegree;
-    s.radius = T::kRadius;
-    s.fma_eval = T::kFmaEval;
+        for (int a = 0; a < 3; ++a) s.shift[m][a] = d.shift[m][a];
+    s.union_taps = d.union_taps;
+    s.taps = d.taps;
+    s.n_reference = d.n_reference;
+    s.degree = d.degree;
+    s.radius = d.radius;
+    s.fma_eval = d.fma_eval;
     // per-axis range of stencil offsets in global axes: reflections and
     // permutations make it the symmetric [-radius, radius]
-    int lo = 0, hi = 0;
-    for (int j = 0; j < T::kTaps; ++j)
-        for (int a = 0; a < 3; ++a) {
-            lo = std::min(lo, (int)T::kOff[j][a]);
-            hi = std::max(hi, (int)T::kOff[j][a]);
-        }
-    s.omin = T::kSymmetry == lsp::kSymNone ? lo : -s.radius;
-    s.omax = T::kSymmetry == lsp::kSymNone ? hi : s.radius;
+    s.omin = d.symmetry == lsp::kSymNone ? d.off_lo : -s.radius;
+    s.omax = d.symmetry == lsp::kSymNone ? d.off_hi : s.radius;
     // an active point's taps reach at most 2 * radius lattice units outside
     // the stored range: ceil(2 radius / D) sites, plus one
     s.pad = (2 * s.radius + s.D - 1) / s.D + 1;
     s.continuity = box_continuity(s.dirs);
     return s;
+}
+
+template <int K>
+SplineDef make_def() {
+    lsp::SplineDesc d;
+    lsp::describe<K>(&d);
+    return def_from_desc(d);
 }
 
 const std::vector<SplineDef>& defs() {
@@ -420,6 +426,32 @@ lsp_status lsp_spline_create(int s, const int32_t* L, const int32_t* Xi, int n_d
                 "8-direction and the FCC 6-direction box splines");
 }
 
+lsp_status lsp_spline_load_plugin(const char* path, lsp_spline** out) {
+    if (!out) return fail(LSP_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!path) return fail(LSP_E_INVALID_ARG, "path is NULL");
+    // kept loaded until the process ends: its kernels back every volume of the spline
+    void* h = dlopen(path, RTLD_NOW | RTLD_LOCAL);
+    if (!h) return fail(LSP_E_UNSUPPORTED, "cannot load %s: %s", path, dlerror());
+    using Describe = int (*)(lsp::SplineDesc*);
+    auto describe = reinterpret_cast<Describe>(dlsym(h, "lsp_plugin_describe"));
+    auto eval = reinterpret_cast<PluginEval>(dlsym(h, "lsp_plugin_eval"));
+    if (!describe || !eval) return fail(LSP_E_UNSUPPORTED, "%s exports no spline plugin entry points", path);
+    lsp::SplineDesc d{};
+    if (describe(&d) != 0 || d.abi != lsp::kPluginAbi)
+        return fail(LSP_E_UNSUPPORTED, "%s was built for another library version (ABI %x, expected %x)", path,
+                    (unsigned)d.abi, (unsigned)lsp::kPluginAbi);
+    if (d.n_dirs < 3 || d.n_dirs > lsp::kDescMaxDirs || d.n_cosets < 1 || d.n_cosets > 4 ||
+        d.lattice < 0 || d.lattice > 2)
+        return fail(LSP_E_UNSUPPORTED, "%s describes an unsupported spline", path);
+    lsp_spline* sp = new (std::nothrow) lsp_spline;
+    if (!sp) return fail(LSP_E_OOM, "host allocation failed");
+    sp->def = def_from_desc(d);
+    sp->def.plugin_eval = eval;
+    *out = sp;
+    return LSP_OK;
+}
+
 void lsp_spline_destroy(lsp_spline* sp) { delete sp; }
 
 static void fill_info(const SplineDef& d, lsp_spline_info* o) {
@@ -547,8 +579,12 @@ static lsp_status run_eval(const lsp_volume* vol, const void* pts, lsp_dtype pd,
     a.split_maxn = split_maxn();
     hipError_t e = hipSuccess;
     bool found = false;
+    if (vol->def.plugin_eval) {
+        e = a.N > 0 ? vol->def.plugin_eval(&a) : hipSuccess;
+        found = true;
+    }
 #define LSP_RUN(k) \
-    if (a.kind == k) { e = lsp::launch_eval<k>(a); found = true; }
+    if (!found && a.kind == k) { e = lsp::launch_eval<k>(a); found = true; }
     LSP_FOR_EACH_KIND(LSP_RUN)
 #undef LSP_RUN
     if (!found) return fail(LSP_E_UNSUPPORTED, "kind %d", a.kind);
@@ -577,7 +613,7 @@ lsp_status lsp_eval_hessian(const lsp_volume* vol, const void* pts, lsp_dtype pt
     lsp_status st = check_eval_args(vol, pts, pts_dtype, N);
     if (st) return st;
     if (vol->def.continuity < 1)
-        return fail(LSP_E_UNSUPPORTED, "%s is only C^%d: no second derivatives", vol->def.name,
+        return fail(LSP_E_UNSUPPORTED, "%s is only C^%d: no second derivatives", vol->def.name.c_str(),
                     vol->def.continuity);
     if (N > 0 && !hess) return fail(LSP_E_INVALID_ARG, "hess is NULL");
     return run_eval(vol, pts, pts_dtype, N, lsp::kValueGradHess, val, grad, nullptr, stream, hess);
@@ -612,6 +648,7 @@ lsp_status lsp_eval_binned_workspace_size(const lsp_volume* vol, lsp_dtype pts_d
                                           size_t* bytes) {
     lsp_status st = check_eval_args(vol, (const void*)1, pts_dtype, N);
     if (st) return st;
+    if (vol->def.plugin_eval) return fail(LSP_E_UNSUPPORTED, "binned order: built-in splines only");
     if (!bytes) return fail(LSP_E_INVALID_ARG, "bytes is NULL");
     *bytes = lsp::binned_workspace_bytes(bin_geom(vol), (int)N, pts_dtype == LSP_F64);
     return LSP_OK;
@@ -622,6 +659,7 @@ lsp_status lsp_eval_binned(const lsp_volume* vol, const void* pts, lsp_dtype pts
                            hipStream_t stream) {
     lsp_status st = check_eval_args(vol, pts, pts_dtype, N);
     if (st) return st;
+    if (vol->def.plugin_eval) return fail(LSP_E_UNSUPPORTED, "binned order: built-in splines only");
     if (N > 0 && !val) return fail(LSP_E_INVALID_ARG, "val is NULL");
     if (N == 0) return LSP_OK;
     lsp::BinnedArgs a{};
@@ -653,6 +691,7 @@ lsp_status lsp_eval_binned(const lsp_volume* vol, const void* pts, lsp_dtype pts
 lsp_status lsp_backward_workspace_size(const lsp_volume* vol, int64_t N, size_t* bytes) {
     if (!vol || !bytes) return fail(LSP_E_INVALID_ARG, "NULL argument");
     if (N < 0 || N >= ((int64_t)1 << 31)) return fail(LSP_E_SHAPE, "N = %lld out of [0, 2^31)", (long long)N);
+    if (vol->def.plugin_eval) return fail(LSP_E_UNSUPPORTED, "dL/dc: built-in splines only");
     const size_t b = lsp::backward_workspace_bytes(vol->def.kind, vol->def.n_cosets, vol->dims,
                                                    vol->def.pad, N);
     if (b == (size_t)-1) return fail(LSP_E_HIP, "sort workspace query failed");
@@ -666,6 +705,7 @@ lsp_status lsp_backward(const lsp_volume* vol, const void* pts, lsp_dtype pts_dt
     lsp_status st = check_eval_args(vol, pts, pts_dtype, N);
     if (st) return st;
     if (N > 0 && !dL_df && (dL_dc || dL_dx)) return fail(LSP_E_INVALID_ARG, "dL_df is NULL");
+    if (dL_dc && vol->def.plugin_eval) return fail(LSP_E_UNSUPPORTED, "dL/dc: built-in splines only");
     if (dL_dx && N > 0) {
         st = run_eval(vol, pts, pts_dtype, N, lsp::kGradX, nullptr, dL_dx, dL_df, stream);
         if (st) return st;
@@ -801,6 +841,7 @@ lsp_status lsp_batch_plan_create(int n_vol, const lsp_volume* const* vols, const
     for (int v = 0; v < n_vol; ++v) {
         const lsp_volume* vol = vols[v];
         if (!vol) return fail(LSP_E_INVALID_ARG, "vols[%d] is NULL", v);
+        if (vol->def.plugin_eval) return fail(LSP_E_UNSUPPORTED, "vols[%d]: batch plans take built-in splines only", v);
         if (N[v] < 0 || N[v] >= ((int64_t)1 << 31)) return fail(LSP_E_SHAPE, "N[%d] out of range", v);
         const bool want_grad = grad && grad[v];
         if (N[v] > 0 && (!pts[v] || (!val[v] && !want_grad)))
@@ -951,6 +992,7 @@ lsp_status lsp_debug_tap_offsets(const lsp_spline* sp, const int64_t dims[3], ls
     size_t nbytes = 0;
     lsp_status st = make_geom(sp->def, dims, ctype, &geom, &nbytes);
     if (st) return st;
+    if (sp->def.plugin_eval) return fail(LSP_E_UNSUPPORTED, "built-in splines only");
 #define LSP_OFFS(k) \
     if (sp->def.kind == k) debug_offsets<k>(geom, pts, N, offs, flags);
     LSP_FOR_EACH_KIND(LSP_OFFS)

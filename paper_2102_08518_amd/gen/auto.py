@@ -29,7 +29,6 @@ from fractions import Fraction as F
 from typing import List, Sequence, Tuple
 
 from .derive import BoxSpline, _floor, polytope_vertices
-from .specs import Region, Spec
 
 HALF = F(1, 2)
 
@@ -89,7 +88,7 @@ def _dot(a, y):
     return sum(F(a[i]) * y[i] for i in range(3))
 
 
-def _knot_planes(bs: BoxSpline, spec: Spec, verts) -> List[Tuple[Tuple[int, ...], F]]:
+def _knot_planes(bs: BoxSpline, spec, verts) -> List[Tuple[Tuple[int, ...], F]]:
     """Every knot plane n . y = t of a stencil translate phi(y - o) that
     crosses the interior of the polytope with vertices verts."""
     lo = [min(v[i] for v in verts) for i in range(3)]
@@ -131,7 +130,7 @@ def _split(halfspaces, planes, leaves):
     return len(leaves) - 1
 
 
-def _cells(spec: Spec, bs: BoxSpline):
+def _cells(spec, bs: BoxSpline):
     dom = _domain(spec.lattice, spec.roe, spec.symmetry)
     planes = _knot_planes(bs, spec, polytope_vertices(dom, 3))
     leaves = []
@@ -139,9 +138,10 @@ def _cells(spec: Spec, bs: BoxSpline):
     return tree, leaves
 
 
-def auto_spec(name: str, lattice: str, Xi: Sequence[Tuple[int, ...]], kind: int = -1) -> Spec:
+def auto_spec(name: str, lattice: str, Xi: Sequence[Tuple[int, ...]], kind: int = -1):
     """The Spec of the box spline with directions Xi on lattice ("cc", "bcc",
     "fcc"), with its sub-regions and region lookup found automatically."""
+    from .specs import Region, Spec  # specs.py builds its own table with this function
     lat = LATTICES[lattice]
     Xi = [tuple(int(v) for v in d) for d in Xi]
     axis_only = all(sum(1 for v in d if v) == 1 for d in Xi)

@@ -1,0 +1,85 @@
+"""GPU parity of a spline compiled at run time (paper_2102_08518_amd.jit):
+the example plugin built by build() -- the piecewise-linear spline on the
+Freudenthal triangulation of Z^3, six reference sub-regions found by the
+automatic analysis -- against the FP64 checker, through the plugin's own
+kernels; and the documented refusals for the paths plugins do not serve."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2102_08518_amd import _native as N
+from paper_2102_08518_amd import api, jit
+
+pytestmark = pytest.mark.gpu
+
+FREUDENTHAL = oracle.Spline("freudenthal", np.eye(3), oracle._cols((1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 1)),
+                            D=(1, 1, 1), shifts=[(0, 0, 0)])
+TORCH_DT = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}
+
+
+def _spline():
+    return api.Spline.from_plugin(jit.build_example(force=False))
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16", "f16"])
+def test_plugin_spline_matches_oracle(device, storage):
+    print("case jit", storage, flush=True)
+    rng = np.random.default_rng(41)
+    E = 12
+    c = rng.uniform(-1, 1, (1, E, E, E))
+    vol = api.Volume(_spline(), (E, E, E), storage)
+    vol.set(torch.tensor(c, dtype=torch.float32, device=device))
+    x = rng.uniform(-2, E + 1, (5001, 3)).astype(np.float32)
+    xt = torch.tensor(x, device=device)
+    f = vol.eval(xt).cpu().numpy()
+    v, g = vol.eval_grad(xt)
+    cs = torch.tensor(c, dtype=torch.float32).to(TORCH_DT[storage]).double().numpy()
+    fref, gref = oracle.evaluate(FREUDENTHAL, (E, E, E), list(cs), x.astype(np.float64), grad=True)
+    assert np.abs(f - fref).max() <= 2e-6
+    assert np.array_equal(f, v.cpu().numpy())
+    # the gradient of a piecewise-linear spline jumps across the tetrahedra:
+    # compare away from the planes x_i = x_j and the cube faces
+    y = x - np.floor(x)
+    gap = np.min(np.abs(np.stack([y[:, 0] - y[:, 1], y[:, 1] - y[:, 2], y[:, 0] - y[:, 2],
+                                  y[:, 0], y[:, 1], y[:, 2], 1 - y[:, 0], 1 - y[:, 1], 1 - y[:, 2]])), axis=0)
+    ok = gap > 1e-4
+    assert ok.sum() > 4000
+    assert np.abs(g.cpu().numpy()[ok] - gref[ok]).max() <= 2e-5
+
+
+def test_plugin_spline_edges_fp64_and_dLdx(device):
+    print("case jit edges", flush=True)
+    rng = np.random.default_rng(42)
+    E = 8
+    c = rng.uniform(-1, 1, (1, E, E, E))
+    vol = api.Volume(_spline(), (E, E, E), "f32")
+    vol.set(torch.tensor(c, dtype=torch.float32, device=device))
+    special = torch.tensor([[np.nan, 1, 1], [np.inf, 2, 2], [1e30, 1, 1], [-40, 2, 2]], dtype=torch.float32,
+                           device=device)
+    f = vol.eval(special).cpu().numpy()
+    assert np.isnan(f[0]) and np.all(f[1:] == 0)
+    assert vol.eval(torch.empty(0, 3, device=device)).shape == (0,)
+    x = rng.uniform(0, E - 1, (3000, 3)) + 1e-3
+    xt = torch.tensor(x, device=device)          # FP64 points
+    ref = oracle.evaluate(FREUDENTHAL, (E, E, E), list(torch.tensor(c, dtype=torch.float32).double().numpy()), x)
+    assert np.abs(vol.eval(xt).cpu().numpy() - ref).max() <= 2e-6
+    gin = torch.tensor(rng.normal(size=3000), dtype=torch.float32, device=device)
+    _, dx = vol.backward(xt, gin, want_dc=False, want_dx=True)
+    _, grad = vol.eval_grad(xt)
+    assert torch.allclose(dx, gin[:, None] * grad, rtol=0, atol=1e-6)
+
+
+def test_plugin_spline_refusals(device):
+    """No Hessian for a C^0 spline; dL/dc, the binned order and batch plans
+    are for the built-in splines only."""
+    print("case jit refusals", flush=True)
+    vol = api.Volume(_spline(), (6, 6, 6), "f32")
+    xt = torch.full((8, 3), 2.5, device=device)
+    for fn in (lambda: vol.eval_hessian(xt),
+               lambda: vol.eval(xt, binned=True),
+               lambda: vol.backward(xt, torch.ones(8, device=device), want_dc=True, want_dx=False),
+               lambda: api.BatchPlan([vol], [xt], [False])):
+        with pytest.raises(N.LspError) as e:
+            fn()
+        assert e.value.status == 2
