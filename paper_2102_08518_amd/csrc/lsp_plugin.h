@@ -16,8 +16,8 @@
 
 namespace lsp {
 
-constexpr int kPluginAbi = 0x4c530100 + (int)sizeof(EvalArgs);
 constexpr int kDescMaxDirs = 16;
+struct SplineDesc;
 
 struct SplineDesc {
     int abi;
@@ -32,6 +32,9 @@ struct SplineDesc {
     int taps, union_taps, n_reference, degree, radius, fma_eval;
     int off_lo, off_hi;            // min / max stencil offset component (reference frame)
 };
+
+// version 1; the struct sizes catch a layout change made without a new version
+constexpr int kPluginAbi = (1 << 24) | ((int)sizeof(EvalArgs) << 12) | (int)sizeof(SplineDesc);
 
 template <int K>
 void describe(SplineDesc* d) {
