@@ -83,3 +83,26 @@ def test_plugin_spline_refusals(device):
         with pytest.raises(N.LspError) as e:
             fn()
         assert e.value.status == 2
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_plugin_of_a_builtin_spline_is_bit_identical(device, storage):
+    """The BCC quartic compiled at run time from (L, Xi) alone (automatic
+    regions, its own plugin library) and the built-in BCC quartic give the
+    same bits: same generated code, same kernels, two code objects."""
+    print("case jit bcc7", storage, flush=True)
+    rng = np.random.default_rng(43)
+    E = 10
+    c = torch.tensor(rng.uniform(-1, 1, (2, E, E, E)), dtype=torch.float32, device=device)
+    plug = api.Volume(api.Spline.from_plugin(jit.build_example(force=False, name="jit_bcc7")), (E, E, E), storage)
+    ref = api.Volume(api.Spline.bcc7(), (E, E, E), storage)
+    plug.set(c)
+    ref.set(c)
+    x = torch.tensor(rng.uniform(-2, 2 * E + 1, (4099, 3)), dtype=torch.float32, device=device)
+    x[::101] = float("nan")
+    eq = lambda a, b: torch.equal(torch.nan_to_num(a, nan=9.0), torch.nan_to_num(b, nan=9.0))
+    assert eq(plug.eval(x), ref.eval(x))
+    for a, b in zip(plug.eval_grad(x), ref.eval_grad(x)):
+        assert eq(a, b)
+    for a, b in zip(plug.eval_hessian(x), ref.eval_hessian(x)):
+        assert eq(a, b)

@@ -56,3 +56,13 @@ def test_plugin_refusals():
     assert e.value.status == 2
     with pytest.raises(ValueError):            # BCC point location needs the full symmetry
         auto_spec("odd", "bcc", [(1, 1, 1), (1, -1, -1), (2, 0, 0)])
+
+
+def test_bcc_plugin_describes_the_builtin_spline():
+    """The BCC quartic compiled as a plugin describes the same spline as the
+    built-in one (kind aside)."""
+    a = api.Spline.from_plugin(jit.build_example(force=False, name="jit_bcc7")).info
+    b = api.Spline.bcc7().info
+    fields = ("n_cosets", "taps", "union_taps", "n_reference", "degree", "radius", "fma_eval", "pad", "continuity")
+    assert [getattr(a, f) for f in fields] == [getattr(b, f) for f in fields]
+    assert list(a.D) == list(b.D) and a.kind == jit.PLUGIN_KIND
