@@ -370,18 +370,30 @@ template <int KIND>
 LSP_HD int tap_offset(const Loc& L, int o0, int o1, int o2, int par) {
     constexpr int LAT = TablesOf<KIND>::kLattice;
     const int o[3] = {o0, o1, o2};
-    int br = 0, in = 0;
+    // For stencils of more than 32 taps each axis contributes its brick and
+    // in-brick bytes as one term, which depends only on that axis' offset
+    // component: with the offsets known at compile time the terms are shared
+    // by every tap with the same component and a tap costs one three-way add
+    // plus its coset (measured on MI355X: 9% faster for the 53-tap spline,
+    // 6% for the 38-tap one; the smaller stencils run faster with the brick
+    // and in-brick sums kept apart).
+    constexpr bool FOLD = TablesOf<KIND>::kTaps > 32;
+    int br = 0, in = 0, off = 0;
     for (int r = 0; r < 3; ++r) {
         int i;
         if (LAT == kLatCC)
             i = L.bidx[0][r] + (TablesOf<KIND>::kSymmetry == kSymNone ? o[r] : mul24s(L.s[r], o[r]));
         else if (LAT == kLatBCC) i = L.bidx[par ? 1 : 0][r] + mul24s(L.s[r], o[r] >> 1);
         else i = L.bidx[o[r] & 1][r] + mul24s(L.s[r], o[r] >> 1);
-        br += brick_term(i, L.lb[r], L.nbs[r]);
-        in += inner_term(i, L.lb[r], L.lis[r]);
+        if (FOLD) {
+            off += (brick_term(i, L.lb[r], L.nbs[r]) << L.lbb) + inner_term(i, L.lb[r], L.lis[r]);
+        } else {
+            br += brick_term(i, L.lb[r], L.nbs[r]);
+            in += inner_term(i, L.lb[r], L.lis[r]);
+        }
     }
     const int cls = (LAT == kLatCC) ? 0 : ((LAT == kLatBCC) ? (par ? 1 : 0) : fcc_class(par));
-    return (br << L.lbb) + in + L.cb[cls];
+    return (FOLD ? off : (br << L.lbb) + in) + L.cb[cls];
 }
 
 // Coset index of a lattice site from the parities of its coordinates.
