@@ -313,7 +313,10 @@ def main():
             # per tap), against the HBM peak; served mostly by L1/L2, not HBM
             "effective_gather_bytes_per_point": 16 + 4 * sp.info.taps,
             "effective_gather_GBs": round((16 + 4 * sp.info.taps) * n / t_k / 1e9, 1),
-            "effective_gather_frac_of_hbm_peak": round((16 + 4 * sp.info.taps) * n / t_k / 1e9 / PEAK_HBM_GBS, 4)}
+            "effective_gather_frac_of_hbm_peak": round((16 + 4 * sp.info.taps) * n / t_k / 1e9 / PEAK_HBM_GBS, 4),
+            # what the counters show binds this kernel (profiles/): the
+            # L1-to-L2 requests of the random stencil gathers, not the VALU
+            "measured_limit": "L1->L2 gather requests (about 9.5 per point); VALU about 38% busy"}
 
     cpu = None
     if not args.no_cpu:
