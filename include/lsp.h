@@ -285,6 +285,9 @@ lsp_status lsp_backward_workspace_size(const lsp_volume* vol, int64_t N, size_t*
  *   workspace, ws_bytes: device scratch of at least
  *          lsp_backward_workspace_size(vol, N) bytes (needed when dL_dc is
  *          requested), aligned to 256 bytes.
+ * Points with a NaN coordinate and points whose stencil misses the stored
+ * lattice (infinite and far coordinates included) add nothing to dL_dc;
+ * their dL_dx is NaN and 0 respectively.  N == 0 gives dL_dc = 0.
  */
 lsp_status lsp_backward(const lsp_volume* vol, const void* pts, lsp_dtype pts_dtype, int64_t N,
                         const float* dL_df, float* dL_dc, float* dL_dx, void* workspace,

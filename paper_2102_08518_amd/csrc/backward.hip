@@ -245,7 +245,7 @@ hipError_t run(const BackwardArgs& a, const Layout& ly) {
     const CellGeom cg = cell_geom(a.dims, a.g.pad, a.n_cosets);
     const int N = a.N;
     const PT* pts = static_cast<const PT*>(a.pts);
-    const int nblk = (N + kBlk - 1) / kBlk;
+    const int nblk = (int)(((long long)N + kBlk - 1) / kBlk);
     if (N > 0) {
         hipLaunchKernelGGL((k_bin_keys<KIND, PT>), dim3(nblk), dim3(kBlk), 0, a.stream, pts, N, a.g,
                            cg, keys_in, vals_in);
@@ -308,7 +308,7 @@ hipError_t launch_dx_from_grad(long long N, const float* dL_df, const float* gra
     if (N <= 0) return hipSuccess;
     if (N > 0x7fffffffLL) return hipErrorInvalidValue;
     const int n = (int)N;
-    hipLaunchKernelGGL(k_dx_from_grad, dim3((n + kBlk - 1) / kBlk), dim3(kBlk), 0, stream, n, dL_df,
+    hipLaunchKernelGGL(k_dx_from_grad, dim3((unsigned)(((long long)n + kBlk - 1) / kBlk)), dim3(kBlk), 0, stream, n, dL_df,
                        grad_f, dL_dx);
     return hipGetLastError();
 }

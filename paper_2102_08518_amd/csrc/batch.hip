@@ -50,11 +50,11 @@ __device__ __forceinline__ void run_item(const BatchVol& v, int start, int count
             return;
         }
     }
-    const int end = start + count;
+    // offsets within the item, so that no index passes 2^31 - 1 on the way
 #pragma unroll 1
-    for (int p = start + (int)threadIdx.x; p < end; p += kBatchBlock)
-        eval_point<KIND, CT, float, MODE, false>(v.pts, p, p, v.coef, v.nbytes, v.g, v.val, v.grad,
-                                                 nullptr);
+    for (int q = (int)threadIdx.x; q < count; q += kBatchBlock)
+        eval_point<KIND, CT, float, MODE, false>(v.pts, start + q, start + q, v.coef, v.nbytes, v.g,
+                                                 v.val, v.grad, nullptr);
 }
 
 template <int KIND, class CT, int MODE>

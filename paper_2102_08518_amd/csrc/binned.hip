@@ -227,7 +227,7 @@ hipError_t run(const BinnedArgs& a, const Parts& q) {
     const int nb1 = a.bg.nbins + 1;
     hipLaunchKernelGGL(k_zero, dim3((nb1 + 255) / 256), dim3(256), 0, a.stream, count, nb1, kCtr);
     const int chunk = kBinBlk * kPtsPerThr;
-    const int cblocks = (N + chunk - 1) / chunk;
+    const int cblocks = (int)(((long long)N + chunk - 1) / chunk);
     hipLaunchKernelGGL((k_bin_count<KIND, PT>), dim3(cblocks), dim3(kBinBlk), nb1 * sizeof(int),
                        a.stream, pts, N, a.g, a.bg, bin, count);
     hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, a.stream, count, nb1, cursor);
@@ -236,7 +236,7 @@ hipError_t run(const BinnedArgs& a, const Parts& q) {
     if constexpr (mfma_eligible<KIND>()) {
         if (a.mfma) {
             const int ppt = N / (256 * 2048) < 1 ? 1 : (N / (256 * 2048) > 8 ? 8 : N / (256 * 2048));
-            const int mblocks = (N + 256 * ppt - 1) / (256 * ppt);
+            const int mblocks = (int)(((long long)N + 256 * ppt - 1) / (256 * ppt));
             if (a.grad)
                 hipLaunchKernelGGL((k_eval_binned_mfma<KIND, CT, PT, kValueGrad>), dim3(mblocks),
                                    dim3(256), 0, a.stream, rec, N, ppt, a.coef, a.nbytes, a.g, a.out,
@@ -250,17 +250,25 @@ hipError_t run(const BinnedArgs& a, const Parts& q) {
     }
     if constexpr (split_eligible<KIND>()) {
         if (N <= split_limit<KIND>(a.split_maxn)) {
-            const int sblocks = (int)(((long long)N * kSplitLanes + 255) / 256);
-            if (a.grad)
-                hipLaunchKernelGGL((k_eval_binned_split<KIND, CT, PT, kValueGrad>), dim3(sblocks),
-                                   dim3(256), 0, a.stream, rec, N, a.coef, a.nbytes, a.g, a.out, a.grad);
-            else
-                hipLaunchKernelGGL((k_eval_binned_split<KIND, CT, PT, kValue>), dim3(sblocks),
-                                   dim3(256), 0, a.stream, rec, N, a.coef, a.nbytes, a.g, a.out, a.grad);
-            return hipGetLastError();
+            // records carry their output index, so a chunk is a range of records
+            for (long long s = 0; s < N; s += kSplitChunk) {
+                const int n = (int)(N - s < kSplitChunk ? N - s : kSplitChunk);
+                const int sblocks = (int)(((long long)n * kSplitLanes + 255) / 256);
+                if (a.grad)
+                    hipLaunchKernelGGL((k_eval_binned_split<KIND, CT, PT, kValueGrad>), dim3(sblocks),
+                                       dim3(256), 0, a.stream, rec + s, n, a.coef, a.nbytes, a.g, a.out,
+                                       a.grad);
+                else
+                    hipLaunchKernelGGL((k_eval_binned_split<KIND, CT, PT, kValue>), dim3(sblocks),
+                                       dim3(256), 0, a.stream, rec + s, n, a.coef, a.nbytes, a.g, a.out,
+                                       a.grad);
+                const hipError_t e = hipGetLastError();
+                if (e != hipSuccess) return e;
+            }
+            return hipSuccess;
         }
     }
-    const int eblocks = (N + 255) / 256;
+    const int eblocks = (int)(((long long)N + 255) / 256);
     if (a.grad)
         hipLaunchKernelGGL((k_eval_binned<KIND, CT, PT, kValueGrad>), dim3(eblocks), dim3(256), 0,
                            a.stream, rec, N, a.coef, a.nbytes, a.g, a.out, a.grad);

@@ -795,7 +795,8 @@ std::vector<lsp::BatchItem> make_items(const std::vector<lsp::BatchVol>& hv, int
             cur = key(v);
             groups->push_back({hv[v].kind, hv[v].ctype, hv[v].grad ? 1 : 0, (int)items.size(), 0});
         }
-        for (int s = 0; s < hv[v].N; s += tile) items.push_back({v, s, std::min(tile, hv[v].N - s)});
+        for (long long s = 0; s < hv[v].N; s += tile)
+            items.push_back({v, (int)s, (int)std::min<long long>(tile, hv[v].N - s)});
         groups->back().count = (int)items.size() - groups->back().first;
     }
     return items;

@@ -23,7 +23,7 @@ hipError_t launch_one(const EvalArgs& a) {
     if constexpr (mfma_eligible<KIND>() && (MODE == kValue || MODE == kValueGrad) && !PRED) {
         if (a.mfma) {
             const int ppt = mfma_points_per_thread(a.N);
-            const int blocks = (a.N + kBlock * ppt - 1) / (kBlock * ppt);
+            const int blocks = (int)(((long long)a.N + kBlock * ppt - 1) / (kBlock * ppt));
             hipLaunchKernelGGL((k_eval_mfma<KIND, CT, PT, MODE>), dim3(blocks), dim3(kBlock), 0,
                                a.stream, static_cast<const PT*>(a.pts), a.N, ppt, a.coef, a.nbytes,
                                a.g, a.out, a.grad);
@@ -32,15 +32,21 @@ hipError_t launch_one(const EvalArgs& a) {
     }
     if constexpr (split_eligible<KIND>() && MODE != kValueGradHess) {
         if (a.N <= split_limit<KIND>(a.split_maxn)) {
-            const long long lanes = (long long)a.N * kSplitLanes;
-            const int blocks = (int)((lanes + kBlock - 1) / kBlock);
-            hipLaunchKernelGGL((k_eval_split<KIND, CT, PT, MODE>), dim3(blocks), dim3(kBlock), 0, a.stream,
-                               static_cast<const PT*>(a.pts), a.N, a.coef, a.nbytes, a.g, a.out, a.grad,
-                               a.gin);
-            return hipGetLastError();
+            const PT* pts = static_cast<const PT*>(a.pts);
+            for (long long s = 0; s < a.N; s += kSplitChunk) {
+                const int n = (int)(a.N - s < kSplitChunk ? a.N - s : kSplitChunk);
+                const int blocks = (int)(((long long)n * kSplitLanes + kBlock - 1) / kBlock);
+                hipLaunchKernelGGL((k_eval_split<KIND, CT, PT, MODE>), dim3(blocks), dim3(kBlock), 0,
+                                   a.stream, pts + 3 * s, n, a.coef, a.nbytes, a.g,
+                                   a.out ? a.out + s : nullptr, a.grad ? a.grad + 3 * s : nullptr,
+                                   a.gin ? a.gin + s : nullptr);
+                const hipError_t e = hipGetLastError();
+                if (e != hipSuccess) return e;
+            }
+            return hipSuccess;
         }
     }
-    const int blocks = (a.N + kBlock - 1) / kBlock;
+    const int blocks = (int)(((long long)a.N + kBlock - 1) / kBlock);
     hipLaunchKernelGGL((k_eval<KIND, CT, PT, MODE, PRED>), dim3(blocks), dim3(kBlock), a.lds_bytes, a.stream,
                        static_cast<const PT*>(a.pts), a.N, a.coef, a.nbytes, a.g, a.out, a.grad,
                        a.gin, a.hess);

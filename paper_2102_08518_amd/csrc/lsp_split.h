@@ -19,6 +19,9 @@
 namespace lsp {
 
 constexpr int kSplitLanes = 4;
+// A launch holds fewer than 2^32 work-items, so the four-lanes-per-point
+// kernels cover more than 2^29 points in launches of 2^29 points each.
+constexpr int kSplitChunk = 1 << 29;
 
 template <int KIND>
 constexpr int split_extent() {

@@ -92,6 +92,55 @@ def test_dLdc_deterministic_and_sum_rules(device, name):
                                atol=1e-5 * tot * pos.max())
 
 
+@pytest.mark.parametrize("name", ["bcc8", "tricubic", "fcc6"])
+def test_dLdc_special_points_add_nothing(device, name):
+    """Points with a NaN or infinite coordinate and far points add nothing to
+    dL/dc: inserting them leaves it bit-identical (the stable sort keeps the
+    order of every cell's points).  Their dL/dx is NaN for a NaN point and 0
+    otherwise.  An empty point set gives dL/dc = 0."""
+    print("case dLdc special points", name, flush=True)
+    E = 8
+    vol, c, x, g = _setup(name, E, 5000, 34, device, outside=False)
+    special = np.array([[np.nan, 1, 1], [1, 1, np.nan], [np.inf, 2, 2], [-np.inf, 2, 2],
+                        [1e30, 1, 1], [3e9, 3e9, 3e9], [-50, 2, 2]], dtype=np.float32)
+    k = 2500
+    xs = np.concatenate([x[:k], special, x[k:]])
+    gs = np.concatenate([g[:k], np.full(len(special), 7.0, np.float32), g[k:]])
+    a, _ = vol.backward(torch.tensor(x, device=device), torch.tensor(g, device=device), want_dx=False)
+    b, dx = vol.backward(torch.tensor(xs, device=device), torch.tensor(gs, device=device))
+    assert torch.equal(a, b)
+    dx = dx.cpu().numpy()[k:k + len(special)]
+    assert np.isnan(dx[:2]).all() and np.all(dx[2:] == 0.0)
+    z, _ = vol.backward(torch.empty(0, 3, device=device), torch.empty(0, device=device),
+                        want_dx=False)
+    assert z.shape == a.shape and int(torch.count_nonzero(z)) == 0
+
+
+@pytest.mark.parametrize("name", ["bcc8", "tricubic"])
+def test_dLdc_all_points_in_one_cell(device, name):
+    """3000 points inside one cell (its thread's loop runs 3000 times):
+    dL/dc still matches the oracle and is reproducible.  The cell is the
+    Voronoi cell of the BCC point (8, 8, 8) and the unit cube [4, 5)^3 of the
+    tricubic spline's floor region of evaluation."""
+    print("case dLdc one cell", name, flush=True)
+    E = 9
+    vol, c, _, _ = _setup(name, E, 1, 35, device, outside=False)
+    rng = np.random.default_rng(36)
+    centre = np.full(3, 8.0 if name == "bcc8" else 4.5)
+    x = (centre + rng.uniform(-0.3, 0.3, (3000, 3))).astype(np.float32)
+    g = rng.normal(size=3000).astype(np.float32)
+    xt, gt = torch.tensor(x, device=device), torch.tensor(g, device=device)
+    dc, _ = vol.backward(xt, gt, want_dx=False)
+    dc2, _ = vol.backward(xt, gt, want_dx=False)
+    assert torch.equal(dc, dc2)
+    dc = dc.cpu().numpy().astype(np.float64)
+    xs = x.astype(np.float64)
+    ref = np.stack(oracle.backward(ORC[name], (E, E, E), xs, g.astype(np.float64)))
+    scale = np.stack(oracle.backward(ORC[name], (E, E, E), xs, np.abs(g).astype(np.float64)))
+    reach = _support_sum(name, E, xs, np.abs(g).astype(np.float64))
+    assert np.all(np.abs(dc - ref) <= 1e-5 * scale + 1e-6 * reach), np.abs(dc - ref).max()
+
+
 def test_permuted_points_give_the_same_dLdc(device):
     """Permuting the input points changes only the summation order within
     a cell, so dL/dc agrees to rounding."""

@@ -103,6 +103,49 @@ def test_value_and_gradient_match_oracle(device, name):
                                atol=2e-5 * float(g.abs().max()))
 
 
+@pytest.mark.parametrize("name", ["bcc8", "tricubic"])
+def test_maximum_point_count(device, name):
+    """N = 2^31 - 1, the largest count the entry points accept (BCC8 on the
+    one-lane path with value and gradient, tricubic on the four-lanes-per-
+    point path): every point is a copy of one interior point except probes
+    at the last indices and where the element index 3i of the point and
+    gradient arrays passes 2^31; each probe's results land at its own index
+    and match the oracle, and sampled copies equal the copy point's value."""
+    print("case maximum N", name, flush=True)
+    N = 2 ** 31 - 1
+    E = 12
+    rng = np.random.default_rng(41)
+    nc = ORC[name].n_cosets
+    c = rng.uniform(-1, 1, (nc, E, E, E))
+    vol = _mk(name, E, c, "f32", device)
+    x = _points(name, E, 65, rng, outside=False)
+    probe = np.array([N - 1, N - 2, N - 255, N - 256, 2 ** 30, (2 ** 31) // 3, (2 ** 31) // 3 + 1,
+                      715827882, 715827883] + list(range(N - 56, N - 256 + 56, -4)), dtype=np.int64)
+    probe = np.unique(probe)
+    assert probe.size <= 64 and probe.max() < N
+    pts = torch.empty(N, 3, dtype=torch.float32, device=device)
+    pts[:] = torch.tensor(x[64], device=device)
+    idx = torch.tensor(probe, device=device)
+    pts[idx] = torch.tensor(x[:probe.size], device=device)
+    ref, gref = oracle.evaluate(ORC[name], (E, E, E), list(_stored(c, "f32")),
+                                np.concatenate([x[:probe.size], x[64:]]).astype(np.float64), grad=True)
+    sample = torch.tensor([0, 1, 12345, 2 ** 29, N - 300], device=device)
+    if name == "bcc8":
+        f, g = vol.eval_grad(pts)
+        gp = g[idx].cpu().numpy()
+        np.testing.assert_allclose(gp, gref[:-1], rtol=0, atol=2e-5)
+        assert torch.all(g[sample] == g[sample[:1]])
+        del g
+    else:
+        f = vol.eval(pts)
+    fp = f[idx].cpu().numpy()
+    assert np.abs(fp - ref[:-1]).max() <= 2e-6
+    fs = f[sample].cpu().numpy()
+    assert np.abs(fs - ref[-1]).max() <= 2e-6 and np.all(fs == fs[0])
+    del f, pts
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("name", ALL)
 def test_edge_inputs(device, name):
     """Empty input, NaN (-> NaN), infinities and far points (-> 0), exact
