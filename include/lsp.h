@@ -332,9 +332,9 @@ typedef struct lsp_batch_plan lsp_batch_plan;  /* opaque: bound work list + capt
  * (volume, tile) items consumed by a persistent grid through an atomic work
  * counter; with LSP_BATCH_AUTOTUNE the tile size and grid size are chosen by
  * timing candidates on `stream` (the outputs are written while doing so).
- * The reset of the work counter and the persistent kernel are captured in a
- * HIP graph.  Allocates the plan's device tables; synchronizes `stream`
- * before returning.
+ * The persistent kernels are captured in a HIP graph; each launch leaves its
+ * work counter at zero for the next.  Allocates the plan's device tables;
+ * synchronizes `stream` before returning.
  */
 lsp_status lsp_batch_plan_create(int n_vol, const lsp_volume* const* vols, const float* const* pts,
                                  const int64_t* N, float* const* val, float* const* grad, int flags,

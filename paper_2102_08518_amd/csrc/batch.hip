@@ -7,9 +7,12 @@
 // Per group one grid of persistent workgroups pops items from the group's
 // atomic counter until its list is exhausted; each variant is its own
 // instantiation, so it keeps the registers of the single-volume kernel
-// instead of the union of all variants.  The counters are reset by a
-// one-thread kernel that runs first on the same stream, so the launches can
-// be captured in a graph and replayed.
+// instead of the union of all variants.  Every workgroup makes exactly one
+// pop past the end of the list, and the workgroup whose pop is the last of
+// all resets the counter to zero: no other workgroup reads it after that, so
+// each launch leaves the counter ready for the next one and a graph of the
+// launches can be replayed without a separate reset.  The counters start at
+// zero when the plan is created.
 #include <hip/hip_runtime.h>
 
 #include "lsp_batch.h"
@@ -70,7 +73,11 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch(const BatchVol* __restric
         // then loaded once into scalar registers
         const int it = __builtin_amdgcn_readfirstlane(s_item);
         __syncthreads();
-        if (it >= n_items) break;
+        if (it >= n_items) {
+            // pops return 0 .. n_items + gridDim.x - 1, each once; the largest is the last
+            if (threadIdx.x == 0 && it == n_items + (int)gridDim.x - 1) atomicExch(counter, 0);
+            break;
+        }
         const BatchItem w = items[it];
         // by reference: the layout fields selected per axis are then read
         // from the descriptor in memory, not from a private copy
@@ -108,8 +115,7 @@ hipError_t launch_group(const BatchVol* vols, const BatchItem* items, const Batc
 hipError_t launch_batch(const BatchVol* vols, const BatchItem* items, const BatchGroup* groups,
                         int n_groups, int* counters, int blocks, int split_maxn, hipStream_t stream) {
     if (n_groups <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, stream, counters, n_groups);
-    hipError_t e = hipGetLastError();
+    hipError_t e = hipSuccess;
     for (int gi = 0; gi < n_groups && e == hipSuccess; ++gi) {
         const BatchGroup& gr = groups[gi];
         if (gr.count <= 0) continue;
@@ -120,6 +126,11 @@ hipError_t launch_batch(const BatchVol* vols, const BatchItem* items, const Batc
 #undef LSP_GROUP
     }
     return e;
+}
+
+hipError_t reset_batch_counters(int* counters, int n, hipStream_t stream) {
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, stream, counters, n);
+    return hipGetLastError();
 }
 
 int batch_block_threads() { return kBatchBlock; }

@@ -870,6 +870,9 @@ lsp_status lsp_batch_plan_create(int n_vol, const lsp_volume* const* vols, const
     // one counter per possible variant (kinds x storages x modes)
     if (e == hipSuccess) e = hipMalloc(&p->d_counter, sizeof(int) * lsp::gen::kNumKinds * 3 * 2);
     if (e != hipSuccess) { destroy_plan(p); return fail(LSP_E_OOM, "hipMalloc: %s", hipGetErrorString(e)); }
+    // every launch leaves its counters at zero again, so they are set once
+    e = lsp::reset_batch_counters(p->d_counter, lsp::gen::kNumKinds * 3 * 2, stream);
+    if (e != hipSuccess) { destroy_plan(p); return hip_fail(e, "counter reset"); }
     e = hipMemcpy(p->d_vols, hv.data(), sizeof(lsp::BatchVol) * n_vol, hipMemcpyHostToDevice);
     if (e != hipSuccess) { destroy_plan(p); return hip_fail(e, "hipMemcpy(vols)"); }
 
@@ -888,13 +891,14 @@ lsp_status lsp_batch_plan_create(int n_vol, const lsp_volume* const* vols, const
     }
     if ((flags & LSP_BATCH_AUTOTUNE) && !cached && total > 0) {
         // time every candidate launch shape on the caller's stream
-        const int tiles[3] = {1024, 4096, 16384};
+        // (256-point tiles let a small batch spread over every CU)
+        const int tiles[4] = {256, 1024, 4096, 16384};
         const int bpcs[3] = {2, 4, 8};
         hipEvent_t t0, t1;
         (void)hipEventCreate(&t0);
         (void)hipEventCreate(&t1);
         float best = 1e30f;
-        for (int ti = 0; ti < 3; ++ti) {
+        for (int ti = 0; ti < 4; ++ti) {
             std::vector<lsp::BatchItem> items = make_items(hv, tiles[ti], &p->groups);
             lsp_status st = upload_items(p, items);
             if (st) { (void)hipEventDestroy(t0); (void)hipEventDestroy(t1); destroy_plan(p); return st; }
@@ -929,7 +933,7 @@ lsp_status lsp_batch_plan_create(int n_vol, const lsp_volume* const* vols, const
     if (st) { destroy_plan(p); return st; }
     p->tile = tile;
     p->blocks = std::max(1, std::min(ncu * bpc, std::max(p->n_items, 1)));
-    // capture reset + persistent kernel into a graph on a private stream
+    // capture the persistent kernels into a graph on a private stream
     e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {

@@ -35,13 +35,16 @@ struct BatchGroup {
     int count;
 };
 
-// Reset the groups' work counters (device, n_groups ints), then run one
-// persistent kernel per group with at most `blocks` workgroups.  All are
-// plain kernel launches (graph-capturable); groups is host memory.
+// One persistent kernel per group with at most `blocks` workgroups, popping
+// items from the group's work counter (device, one int per group), which
+// must be zero before the launch and is zero again after it.  Plain kernel
+// launches (graph-capturable); groups is host memory.
 // split_maxn: the four-lanes-per-point limit of the separable splines, as
 // for the direct entry points (-1: each spline's default).
 hipError_t launch_batch(const BatchVol* vols, const BatchItem* items, const BatchGroup* groups,
                         int n_groups, int* counters, int blocks, int split_maxn, hipStream_t stream);
+// Set n work counters to zero (once, when a plan is created).
+hipError_t reset_batch_counters(int* counters, int n, hipStream_t stream);
 int batch_block_threads();
 
 }  // namespace lsp
