@@ -185,6 +185,131 @@ def run_orders(args, dev, stream):
                       "lattice_extent": inputs.ORDERS_E, "results": out_all}), flush=True)
 
 
+def sampled_errors(name, E, c, x, outs, m, seed=12):
+    """Max |f - f_ref| / max|c| over a seeded sample of m points, against the
+    FP64 checker run on the coefficients as stored (per storage type in outs)
+    and on the unrounded FP64 coefficients."""
+    import torch
+    import oracle
+    orc = {"tricubic": oracle.TRICUBIC, "bcc8": oracle.BCC8, "fcc6": oracle.FCC6}[name]
+    tdt = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}
+    idx = np.random.default_rng(seed).choice(x.shape[0], min(m, x.shape[0]), replace=False)
+    xs = x[idx].astype(np.float64)
+    cmax = float(np.abs(c).max())
+    ref64 = oracle.evaluate(orc, (E, E, E), list(np.asarray(c, dtype=np.float64)), xs)
+    err = {}
+    for st, f in outs.items():
+        cs = torch.tensor(c, dtype=torch.float32).to(tdt[st]).double().numpy()
+        ref = oracle.evaluate(orc, (E, E, E), list(cs), xs)
+        err[st] = dict(max_rel_vs_stored=float(np.abs(f[idx] - ref).max() / cmax),
+                       max_rel_vs_fp64=float(np.abs(f[idx] - ref64).max() / cmax))
+    return err
+
+
+def run_configs(args, dev, stream):
+    """The other workloads, one JSON line: tricubic Z^3 32^3 with 10^5 points
+    (eager launches and a one-volume batch plan replayed as a graph); FCC6 on
+    4 x 128^3 along 2^24 coherent ray samples, FP32 / BF16 / FP16 storage;
+    BCC8 on 2 x 96^3 with 2^23 points, one forward + backward step and one
+    Adam step of the fit; 64 volumes of uneven size (tricubic and BCC8,
+    2.06e7 points) through one batch plan, value and value + gradient.
+    Sampled errors against the FP64 checker unless --no-cpu."""
+    import torch
+    from paper_2102_08518_amd import api, inputs
+
+    res = {}
+    # tricubic, 10^5 points: launch-bound
+    w = inputs.workload1()
+    E, c, x = w["E"], w["coeffs"], w["points"]
+    vol = api.Volume(api.Spline.tricubic(), (E,) * 3, "f32")
+    vol.set(torch.tensor(c, dtype=torch.float32, device=dev))
+    xt = torch.tensor(x, device=dev)
+    o = torch.empty(x.shape[0], device=dev)
+    ms = time_fn(lambda: vol.eval(xt, o), 10 * args.steps, args.warmup, stream)
+    plan = api.BatchPlan([vol], [xt], [False], autotune=True)
+    ms_g = time_fn(plan.run, 10 * args.steps, args.warmup, stream)
+    vol.eval(xt, o)
+    r = dict(points=x.shape[0], ms=round(ms, 5), pts_per_s=round(x.shape[0] / (ms * 1e-3)),
+             ms_graph=round(ms_g, 5), pts_per_s_graph=round(x.shape[0] / (ms_g * 1e-3)))
+    if not args.no_cpu:
+        r["err"] = sampled_errors("tricubic", E, c, x, {"f32": o.double().cpu().numpy()}, m=400)["f32"]
+    res["tricubic_cc32_1e5"] = r
+    log("tricubic 32^3, 1e5 points: %.4f ms per call, %.4f ms per graph replay" % (ms, ms_g))
+    del plan, vol, xt, o
+
+    # FCC6 rays, three storage types
+    w = inputs.workload3()
+    E, c, x = w["E"], w["coeffs"], w["points"]
+    xt = torch.tensor(x, device=dev)
+    o = torch.empty(x.shape[0], device=dev)
+    for st in ("f32", "bf16", "f16"):
+        vol = api.Volume(api.Spline.fcc6(), (E,) * 3, st)
+        vol.set(torch.tensor(c, dtype=torch.float32, device=dev))
+        ms = time_fn(lambda: vol.eval(xt, o), args.steps, args.warmup, stream)
+        vol.eval(xt, o)
+        r = dict(points=x.shape[0], ms=round(ms, 5), pts_per_s=round(x.shape[0] / (ms * 1e-3)))
+        if not args.no_cpu:
+            r["err"] = sampled_errors("fcc6", E, c, x, {st: o.double().cpu().numpy()}, m=400)[st]
+        res["fcc6_fcc128_rays_" + st] = r
+        log("fcc6 rays %s: %.4f ms, %.3e points/s" % (st, ms, x.shape[0] / (ms * 1e-3)))
+        del vol
+    del xt, o
+
+    # BCC8 2 x 96^3 fit: forward + backward step and Adam step
+    w = inputs.workload4()
+    E, x, y = w["E"], w["points"], w["targets"]
+    vol = api.Volume(api.Spline.bcc8(), (E,) * 3, "f32")
+    ct = torch.zeros(2, E, E, E, device=dev, requires_grad=True)
+    opt = torch.optim.Adam([ct], lr=0.05)
+    xt = torch.tensor(x, device=dev)
+    yt = torch.tensor(y, device=dev)
+
+    def fit_step():
+        opt.zero_grad()
+        f = api.LatticeSplineFn.apply(xt, ct, vol)
+        loss = ((f - yt) ** 2).mean()
+        loss.backward()
+        opt.step()
+        return loss
+
+    losses = [float(fit_step().detach()) for _ in range(5)]
+    ms_adam = time_fn(fit_step, max(args.steps // 5, 3), 1, stream)
+    g = torch.empty(x.shape[0], device=dev).uniform_(-1e-6, 1e-6)
+    ws = torch.empty(vol.workspace_bytes(x.shape[0]) + 256, dtype=torch.uint8, device=dev)
+
+    def fwd_bwd():
+        _, gr = vol.eval_grad(xt)
+        vol.backward(xt, g, workspace=ws, grad_f=gr)
+
+    ms_fb = time_fn(fwd_bwd, max(args.steps // 5, 3), 2, stream)
+    res["bcc8_bcc96_fit_8M"] = dict(points=x.shape[0], ms_fwd_bwd=round(ms_fb, 5),
+                                    pts_per_s_fwd_bwd=round(x.shape[0] / (ms_fb * 1e-3)),
+                                    ms_adam_step=round(ms_adam, 5),
+                                    first_losses=[round(v, 6) for v in losses])
+    log("bcc8 2x96^3 fit: fwd+bwd %.4f ms, Adam step %.4f ms" % (ms_fb, ms_adam))
+    del vol, ct, opt, xt, yt, g, ws
+
+    # 64 volumes through one batch plan
+    wl = inputs.workload5()
+    vols, pts = [], []
+    for d in wl:
+        v = api.Volume(api.Spline.named(d["spline"]), (d["E"],) * 3, "f32")
+        v.set(torch.tensor(d["coeffs"], device=dev))
+        vols.append(v)
+        pts.append(torch.tensor(d["points"], device=dev))
+    ntot = sum(d["n"] for d in wl)
+    for mode in ("value", "value+grad"):
+        plan = api.BatchPlan(vols, pts, [mode != "value"] * len(vols), autotune=True)
+        ms = time_fn(plan.run, args.steps, args.warmup, stream)
+        res["batch64_" + mode] = dict(points=ntot, volumes=len(vols), ms=round(ms, 5),
+                                      pts_per_s=round(ntot / (ms * 1e-3)), tile=plan.tile,
+                                      blocks=plan.blocks)
+        log("batch of %d volumes, %s: %.4f ms, %.3e points/s" % (len(vols), mode, ms, ntot / (ms * 1e-3)))
+    print(json.dumps({"mode": "configs", "unit": "points/s", "storage": "f32 unless named",
+                      "steps": args.steps, "warmup": args.warmup, "data": "synthetic",
+                      "results": res}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -199,6 +324,10 @@ def main():
                     help="instead of the headline line: the order-2/3/4 spline comparisons of the "
                          "paper's experiments (equal-memory lattices, 10^6 random points), one JSON "
                          "line with points/s per spline")
+    ap.add_argument("--configs", action="store_true",
+                    help="instead of the headline line: the other workloads (tricubic 32^3 with "
+                         "10^5 points, FCC6 rays on 4x128^3, the BCC8 2x96^3 fit, a batch of 64 "
+                         "volumes), one JSON line")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/traffic.json from the rocprofv3 output directories of a "
                          "--pmc FETCH_SIZE and a --pmc WRITE_SIZE run of this script (no GPU)")
@@ -218,6 +347,9 @@ def main():
     stream = torch.cuda.current_stream(dev)
     if args.orders:
         run_orders(args, dev, stream)
+        return
+    if args.configs:
+        run_configs(args, dev, stream)
         return
     if args.copy_probe:
         src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
@@ -282,19 +414,11 @@ def main():
     except Exception as e:  # the backward coefficient pass may be unavailable
         log("fwd+bwd not measured: %s" % e)
 
-    # accuracy against the FP64 checker on a seeded sample
-    import oracle
-    rng = np.random.default_rng(12)
-    idx = rng.choice(n, 512, replace=False)
-    cmax = float(np.abs(c).max())
-    err = {}
-    for storage, tdt in (("f32", torch.float32), ("bf16", torch.bfloat16)):
-        cs = torch.tensor(c, dtype=torch.float32).to(tdt).double().numpy()
-        ref = oracle.evaluate(oracle.BCC8, (E, E, E), list(cs), x[idx].astype(np.float64))
-        ref64 = oracle.evaluate(oracle.BCC8, (E, E, E), list(c), x[idx].astype(np.float64))
-        f = res[storage]["f"][idx]
-        err[storage] = dict(max_rel_vs_stored=float(np.abs(f - ref).max() / cmax),
-                            max_rel_vs_fp64=float(np.abs(f - ref64).max() / cmax))
+    # the CPU leg (skipped with --no-cpu): accuracy against the FP64 checker
+    # on a seeded sample, then the checker's own throughput
+    err = {"f32": None, "bf16": {"max_rel_vs_stored": None, "max_rel_vs_fp64": None}}
+    if not args.no_cpu:
+        err = sampled_errors("bcc8", E, c, x, {st: res[st]["f"] for st in ("f32", "bf16")}, m=512)
 
     ms = res["f32"]["ms"]
     t_k = ms * 1e-3
@@ -320,6 +444,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
+        import oracle
         m = args.cpu_sample
         sub = x[:m].astype(np.float64)
         t0 = time.time()
