@@ -71,9 +71,19 @@ __device__ __forceinline__ void gather(const Loc& L, __amdgpu_buffer_rsrc_t r, f
     for (int j = 0; j < T::kTaps; ++j)
         off[j] = tap_offset<KIND>(L, T::kOff[j][0], T::kOff[j][1], T::kOff[j][2], T::kParity[j]);
     __builtin_amdgcn_sched_barrier(0);
+    if constexpr (FENCE_AFTER) {
+        // the polynomial waits for every load: table order, which keeps the
+        // loads of neighbouring taps together
 #pragma unroll
-    for (int j = 0; j < T::kTaps; ++j) c[j] = Coef<CT>::ld(r, off[j]);
-    if constexpr (FENCE_AFTER) __builtin_amdgcn_sched_barrier(0);
+        for (int j = 0; j < T::kTaps; ++j) c[j] = Coef<CT>::ld(r, off[j]);
+        __builtin_amdgcn_sched_barrier(0);
+    } else {
+        // the polynomial starts while loads are in flight, and loads complete
+        // in issue order: issue them in the order the polynomial first reads
+        // the taps (generated)
+#pragma unroll
+        for (int q = 0; q < T::kTaps; ++q) c[T::kIssue[q]] = Coef<CT>::ld(r, off[T::kIssue[q]]);
+    }
 }
 
 // Reference polynomial value and gradient (the unrolled reference

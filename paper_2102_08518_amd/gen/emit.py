@@ -22,6 +22,7 @@ from __future__ import annotations
 import itertools
 import json
 import os
+import re
 from fractions import Fraction
 from typing import Dict, List, Sequence, Tuple
 
@@ -378,6 +379,10 @@ class SplineCode:
         par = ", ".join(str((o[0] & 1) | ((o[1] & 1) << 1) | ((o[2] & 1) << 2)) for o in self.union)
         L.append("  // parity pattern of each offset: bit0 x, bit1 y, bit2 z")
         L.append("  static constexpr unsigned char kParity[kTaps] = {%s};" % par)
+        L.append("  // order in which the gather issues the tap loads: the order in which the")
+        L.append("  // code of the first sub-region's polynomial first reads them (loads complete")
+        L.append("  // in issue order, so the polynomial can start on the first ones)")
+        L.append("  static constexpr unsigned char kIssue[kTaps] = {%s};" % ", ".join(str(j) for j in self.issue_order()))
         for k, d in enumerate(self.regions):
             mask = sum(1 << self.union.index(o) for o in d.taps)
             L.append("  static constexpr unsigned long long kRegionMask%d = 0x%xull;" % (k, mask))
@@ -412,9 +417,35 @@ class SplineCode:
         mons = sorted(set().union(*[set(q.t) for q in loc]), key=lambda e: (-sum(e), e))
         return loc, uidx, mons, {e: i for i, e in enumerate(mons)}
 
+    def issue_order(self) -> List[int]:
+        """Union tap indices in the order the emitted coefficient code of
+        sub-region 0 first reads them, then any taps it does not read; table
+        order for the separable splines (their code reads the taps slab by
+        slab in table order)."""
+        n = len(self.union)
+        if self.tensor is not None:
+            return list(range(n))
+        temps, rows = self._coef_cse(0)
+        text = [lin_comb([(vi, F(1)), (vj, ratio)]) for _, vi, vj, ratio in temps]
+        text += [lin_comb(sorted(row.items())) for row in rows]
+        order = []
+        for expr in text:
+            for tok in re.findall(r"\bc\[(\d+)\]", expr):
+                if int(tok) not in order:
+                    order.append(int(tok))
+        order += [j for j in range(n) if j not in order]
+        return order
+
     def _coef_cse(self, k: int):
         """Monomial coefficients of sub-region k (row m = A[m], over the
         fetched values c[j] of the union stencil) after pair elimination."""
+        memo = self.__dict__.setdefault("_cse_memo", {})
+        if k in memo:
+            return memo[k]
+        memo[k] = self._coef_cse_uncached(k)
+        return memo[k]
+
+    def _coef_cse_uncached(self, k: int):
         loc, uidx, mons, midx = self._region_terms(k)
         rows = [{"c[%d]" % uidx[j]: q.t[e] for j, q in enumerate(loc) if e in q.t} for e in mons]
         temps, new = cse_pairs(rows)
