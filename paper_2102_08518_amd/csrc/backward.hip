@@ -163,19 +163,25 @@ __global__ __launch_bounds__(kBlk) void k_site_gather(const float* __restrict__ 
     // lattice position of the site: D * idx + shift_m
     const int n0 = D * ix + T::kShift[m][0], n1 = D * iy + T::kShift[m][1],
               n2 = D * iz + T::kShift[m][2];
+    // every slot's read is independent, so the loop is unrolled whole and all
+    // reads can be in flight together; slots outside the cell grid read cell 0
+    // and add +0,
+    // which leaves the sum unchanged (it starts at +0 and never becomes -0),
+    // so the summation order and the result are those of the plain loop
     float acc = 0.0f;
-#pragma unroll 4
+#pragma unroll
     for (int u = 0; u < T::kNumU; ++u) {
         const int c0 = n0 - T::kU[u][0], c1 = n1 - T::kU[u][1], c2 = n2 - T::kU[u][2];
         const int K0 = D == 1 ? c0 : (c0 >> 1);
         const int K1 = D == 1 ? c1 : (c1 >> 1);
         const int K2 = D == 1 ? c2 : (c2 >> 1);
-        if (K0 < -cg.pad || K0 >= cg.PX - cg.pad || K1 < -cg.pad || K1 >= cg.PY - cg.pad ||
-            K2 < -cg.pad || K2 >= cg.PZ - cg.pad)
-            continue;
+        const bool inside = K0 >= -cg.pad && K0 < cg.PX - cg.pad && K1 >= -cg.pad &&
+                            K1 < cg.PY - cg.pad && K2 >= -cg.pad && K2 < cg.PZ - cg.pad;
         const int cm = coset_of_parity<KIND>(c0 & 1, c1 & 1, c2 & 1);
         const int cell = cm * cg.NC + ((K2 + cg.pad) * cg.PY + (K1 + cg.pad)) * cg.PX + (K0 + cg.pad);
-        acc += P[(size_t)u * cg.ncell + cell];
+        // the read itself stays inside P for every slot (cell 0 when outside)
+        const float v = P[(size_t)u * cg.ncell + (inside ? cell : 0)];
+        acc += inside ? v : 0.0f;
     }
     dL_dc[s] = acc;
 }
