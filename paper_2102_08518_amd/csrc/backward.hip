@@ -103,7 +103,7 @@ __global__ __launch_bounds__(kPartBlk) void k_cell_partials(const PT* __restrict
     constexpr int NU = T::kNumU;
     constexpr int NT = T::kTaps;
     constexpr int SLOTS = NU | 1;   // odd stride between threads' slots
-    __shared__ unsigned char Uinv[T::kNumSym * NT];
+    __shared__ __attribute__((aligned(16))) unsigned char Uinv[T::kNumSym * NT];
     __shared__ float acc[kPartBlk * SLOTS];
     for (int t = threadIdx.x; t < T::kNumSym * NU; t += kPartBlk) {
         const int sg = t / NU, u = t % NU;
@@ -125,8 +125,32 @@ __global__ __launch_bounds__(kPartBlk) void k_cell_partials(const PT* __restrict
         tap_weights<KIND>(L, w);
         const float gi = gin[i];
         const unsigned char* ui = Uinv + sym_id<KIND>(L) * NT;
+        if constexpr (NT % 16 == 0) {
+            // The taps of one point land in distinct slots (u(G, j) is
+            // one-to-one in j for a fixed symmetry G), so all slots are read,
+            // updated and written back as independent batches instead of a
+            // chain of dependent read-modify-writes; each slot gets the same
+            // add.  The row of slot indices is read as 16-byte words (rows
+            // are 16-byte aligned).
+            int slot[NT];
 #pragma unroll
-        for (int j = 0; j < NT; ++j) mine[ui[j]] += gi * w[j];
+            for (int q = 0; q < NT / 16; ++q) {
+                const uint4 v = reinterpret_cast<const uint4*>(ui)[q];
+                const unsigned wv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int t = 0; t < 16; ++t) slot[16 * q + t] = (wv[t >> 2] >> (8 * (t & 3))) & 0xff;
+            }
+            float a[NT];
+#pragma unroll
+            for (int j = 0; j < NT; ++j) a[j] = mine[slot[j]];
+#pragma unroll
+            for (int j = 0; j < NT; ++j) a[j] += gi * w[j];
+#pragma unroll
+            for (int j = 0; j < NT; ++j) mine[slot[j]] = a[j];
+        } else {
+#pragma unroll
+            for (int j = 0; j < NT; ++j) mine[ui[j]] += gi * w[j];
+        }
     }
     if (c >= ncell) return;
     for (int u = 0; u < NU; ++u) P[(size_t)u * ncell + c] = mine[u];
